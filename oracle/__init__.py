@@ -1,0 +1,17 @@
+"""CPU FP64 oracle for the boundary-MPS branch-and-bound method.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library; both sides take the same seeded instances from ``tnb_inputs``.
+
+Modules
+  ising   -- Eq. (1), (6), (10): energies, brute-force Z / marginals / ground
+             states, closed forms.
+  potts   -- Eq. (3)-(5): cluster tables E_n[x], projectors, compressed bond
+             tables.
+  bmps    -- Sec. III.B-C: PEPS row transfer, zipper with randomized SVD,
+             truncation, log Z.
+  search  -- Sec. III.A, Eq. (7)-(9): conditional marginals from the
+             boundary MPS and branch and bound with boundary merging.
+"""

@@ -1,0 +1,374 @@
+"""Boundary-MPS approximation of the lower half of the PEPS (Sec. III.B-C).
+
+Tensor network (one fixed decomposition; the paper's Fig. 5 and A6 are not
+recoverable).  The boundary MPS Psi_r stands for all rows >= r as a function
+of the configuration of row r-1 and has 2C-1 sites:
+  site 2c   : v_c = P^{(r-1,c),(r,c)} x_{r-1,c}                (vertical bond)
+  site 2c+1 : (a_c, b_c) = (P^{(r-1,c),(r,c+1)} x_{r-1,c},
+                            P^{(r-1,c+1),(r,c)} x_{r-1,c+1})   (two diagonals)
+              stored as the index a_c + d_a * b_c.
+Row r is an MPO of site tensors S_c (which trace x_{r,c} out) and mediating
+tensors M_c (which carry the horizontal and both diagonal couplings between
+columns c and c+1).  The MPO bond between S_c and M_c is rho = P^R x_{r,c},
+the spins of (r,c) coupled to any cluster of column c+1; between M_c and
+S_{c+1} it is l = P^L x_{r,c+1}.  Site and mediating tensors are never built:
+every use goes through the diagrams below, which enumerate x (site) or
+(rho, l) (mediating), as in Fig. 7.
+
+Psi_R = 1 and Psi_r = compress_chi(T_r Psi_{r+1}) for r = R-1 .. 1, where
+compress is the zipper of Fig. 8: MPO tensors are attached right to left to
+the left-canonical Psi_{r+1}; at each site the dashed-box operator is
+truncated by a randomized SVD targeting 2 chi singular values (matrix-free,
+Halko et al.); afterwards a left-to-right SVD sweep truncates to chi.  All
+Boltzmann tables are shifted by their minimum energy (per-table log-scale).
+"""
+import numpy as np
+
+from .potts import Potts, pext, pdep, popcount
+
+SPLITMIX_GOLDEN = 0x9E3779B97F4A7C15
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(c):
+    """SplitMix64 output for counter c (vectorised over uint64)."""
+    z = np.asarray(c, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z + np.uint64(1)) * np.uint64(SPLITMIX_GOLDEN)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def rademacher(n_rows, n_cols, seed, r, k):
+    """+-1 test matrix: entry (i, j) is + iff the top bit of
+    splitmix64(key + i*n_cols + j) is set, key = splitmix64((seed<<24)+(r<<12)+k)."""
+    key = splitmix64(np.uint64(((int(seed) << 24) + (r << 12) + k) & MASK64))
+    idx = np.arange(n_rows * n_cols, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = splitmix64(key + idx)
+    return np.where((z >> np.uint64(63)) == 1, 1.0, -1.0).reshape(n_rows, n_cols)
+
+
+def orth(Y, cut):
+    """Orthonormal basis of the numerical range of Y (singular values above
+    cut * the largest), zero-padded to Y's column count."""
+    out = np.zeros_like(Y)
+    if Y.size == 0:
+        return out
+    U, s, _ = np.linalg.svd(Y, full_matrices=False)
+    if s[0] <= 0:
+        return out
+    keep = s > cut * s[0]
+    out[:, :int(keep.sum())] = U[:, keep]
+    return out
+
+
+def rsvd(apply, applyT, n_rows, n_cols, t, width, power, cut, seed, r, k):
+    """Randomized truncated SVD of the implicit n_rows x n_cols operator D.
+
+    Range finder Y = D Omega (Omega Rademacher, or the identity when D has no
+    more columns than the sketch), `power` subspace iterations, Q = orth(Y),
+    B = Q^T D, B = U S V^T; returns Q U[:, :t], S[:t], V^T[:t] with singular
+    triplets below cut * S[0] set to zero.
+    """
+    if n_cols <= width:
+        Y = apply(np.eye(n_cols))
+        iters = 0
+    else:
+        Y = apply(rademacher(n_cols, width, seed, r, k))
+        iters = power
+    for _ in range(iters):
+        Z = applyT(orth(Y, cut))
+        Y = apply(orth(Z, cut))
+    Q = orth(Y, cut)
+    B = applyT(Q).T                     # (s, n_cols) = Q^T D
+    Ub, S, Vt = np.linalg.svd(B, full_matrices=False)
+    S = S[:t].copy()
+    Ub = Ub[:, :t].copy()
+    Vt = Vt[:t].copy()
+    if S.size and S[0] > 0:
+        drop = S <= cut * S[0]
+    else:
+        drop = np.ones(S.shape, dtype=bool)
+    S[drop] = 0.0
+    Ub[:, drop] = 0.0
+    Vt[drop, :] = 0.0
+    if S.size < t:                      # fewer singular values than the target
+        pad = t - S.size
+        S = np.concatenate([S, np.zeros(pad)])
+        Ub = np.concatenate([Ub, np.zeros((Ub.shape[0], pad))], axis=1)
+        Vt = np.concatenate([Vt, np.zeros((pad, Vt.shape[1]))], axis=0)
+    return Q @ Ub, S, Vt
+
+
+def _segment_sum(vals, idx, n):
+    """out[g] = sum of vals[i] with idx[i] == g (first axis)."""
+    out = np.zeros((n,) + vals.shape[1:])
+    if len(idx) == 0:
+        return out
+    order = np.argsort(idx, kind="stable")
+    si = idx[order]
+    starts = np.flatnonzero(np.r_[True, si[1:] != si[:-1]])
+    out[si[starts]] = np.add.reduceat(vals[order], starts, axis=0)
+    return out
+
+
+class Network:
+    """Boltzmann tables of one instance at inverse temperature beta (Eq. 6),
+    each shifted by its minimum energy; `shift` is the total log-scale."""
+
+    def __init__(self, inst, beta):
+        self.P = P = Potts(inst)
+        self.beta = beta
+        self.R, self.C = P.R, P.C
+        self.w = []
+        shift = 0.0
+        for n in range(P.R * P.C):
+            E = P.local_energy(n)
+            Emin = E.min()
+            shift += -beta * Emin
+            self.w.append(np.exp(-beta * (E - Emin)))
+        self.W = {}
+        for (m, n) in P.inter:
+            Eb = P.bond_energy(m, n)
+            Emin = Eb.min()
+            shift += -beta * Emin
+            self.W[(m, n)] = np.exp(-beta * (Eb - Emin))
+            self.W[(n, m)] = self.W[(m, n)].T
+        self.shift = shift
+
+    def cell(self, r, c):
+        if 0 <= r < self.R and 0 <= c < self.C:
+            return r * self.C + c
+        return -1
+
+    def B(self, m, n):
+        return self.P.B(m, n) if (m >= 0 and n >= 0) else 0
+
+    def Wt(self, m, n):
+        """Bond weight table W[P^{mn} x_m, P^{nm} x_n] (ones(1,1) if none)."""
+        if m < 0 or n < 0 or (m, n) not in self.W:
+            return np.ones((1 << popcount(self.B(m, n)), 1 << popcount(self.B(n, m))))
+        return self.W[(m, n)]
+
+    # ---- boundary-MPS physical dimensions for the cut above row r ----------
+    def phys_dims(self, r):
+        """Physical dims of Psi_r (2C-1 sites) and the (d_a, d_b) split."""
+        C = self.C
+        dims, split = [], []
+        for c in range(C):
+            up, lo = self.cell(r - 1, c), self.cell(r, c)
+            dims.append(1 << popcount(self.B(up, lo)))
+            split.append(None)
+            if c + 1 < C:
+                da = 1 << popcount(self.B(self.cell(r - 1, c), self.cell(r, c + 1)))
+                db = 1 << popcount(self.B(self.cell(r - 1, c + 1), self.cell(r, c)))
+                dims.append(da * db)
+                split.append((da, db))
+        return dims, split
+
+    def PL(self, r, c):
+        n = self.cell(r, c)
+        return (self.B(n, self.cell(r - 1, c - 1)) | self.B(n, self.cell(r, c - 1))
+                | self.B(n, self.cell(r + 1, c - 1)))
+
+    def PR(self, r, c):
+        n = self.cell(r, c)
+        return (self.B(n, self.cell(r - 1, c + 1)) | self.B(n, self.cell(r, c + 1))
+                | self.B(n, self.cell(r + 1, c + 1)))
+
+
+def sub(y, outer, inner):
+    """Bits `inner` (subset of `outer`) of a value y = pext(x, outer)."""
+    return pext(pdep(y, outer), inner)
+
+
+class RowOps:
+    """Diagram data for the row-r MPO (site tensors S_c, mediating M_c)."""
+
+    def __init__(self, net, r):
+        self.net, self.r = net, r
+        C = net.C
+        self.site = []
+        for c in range(C):
+            n = net.cell(r, c)
+            up = net.cell(r - 1, c)
+            k = int(net.P.k[n])
+            x = np.arange(1 << k, dtype=np.int64)
+            PL, PR = net.PL(r, c), net.PR(r, c)
+            self.site.append(dict(
+                w=net.w[n], x=x,
+                u=pext(x, net.B(n, up)),                       # spins facing the upper cell
+                Wv=net.Wt(up, n),                              # [v, u]
+                vd=pext(x, net.B(n, net.cell(r + 1, c))),      # Psi_{r+1} site 2c index
+                l=pext(x, PL), rho=pext(x, PR),
+                dL=1 << popcount(PL), dR=1 << popcount(PR), PL=PL, PR=PR))
+        self.med = []
+        for c in range(C - 1):
+            n0, n1 = net.cell(r, c), net.cell(r, c + 1)
+            PR0, PL1 = net.PR(r, c), net.PL(r, c + 1)
+            rho = np.arange(1 << popcount(PR0))
+            ell = np.arange(1 << popcount(PL1))
+            Wh = net.Wt(n0, n1)[sub(rho, PR0, net.B(n0, n1))[:, None],
+                                sub(ell, PL1, net.B(n1, n0))[None, :]]
+            up0, up1 = net.cell(r - 1, c), net.cell(r - 1, c + 1)
+            Wdr = net.Wt(up0, n1)[:, sub(ell, PL1, net.B(n1, up0))]   # [a, l]
+            Wdl = net.Wt(up1, n0)[:, sub(rho, PR0, net.B(n0, up1))]   # [b, rho]
+            a2 = sub(rho, PR0, net.B(n0, net.cell(r + 1, c + 1)))      # Psi_{r+1} a'
+            b2 = sub(ell, PL1, net.B(n1, net.cell(r + 1, c)))          # Psi_{r+1} b'
+            da2 = 1 << popcount(net.B(n0, net.cell(r + 1, c + 1)))
+            self.med.append(dict(Wh=Wh, Wdr=Wdr, Wdl=Wdl, a2=a2, b2=b2, da2=da2,
+                                 dR=len(rho), dL=len(ell),
+                                 da=Wdr.shape[0], db=Wdl.shape[0]))
+
+    # ---- site diagram (Fig. 7a,b) ------------------------------------------
+    def site_apply(self, c, A, K, X):
+        """(D X)[alpha, l, j] for the dashed box A_{2c} . S_c . K.
+        A: (Da, d_v', Db); K: (Db, dR, Dg); X: (d_v, Dg, s)."""
+        S = self.site[c]
+        Xt = np.einsum("vu,vgj->ugj", S["Wv"], X)                  # W_v folded into X
+        T = np.einsum("bxg,xgj->xbj", K[:, S["rho"], :], Xt[S["u"]])
+        Y = np.einsum("axb,xbj->xaj", A[:, S["vd"], :], T) * S["w"][:, None, None]
+        out = _segment_sum(Y, S["l"], S["dL"])                     # (dL, Da, s)
+        return np.transpose(out, (1, 0, 2))
+
+    def site_applyT(self, c, A, K, Y):
+        """(D^T Y)[v, gamma, j];  Y: (Da, dL, s)."""
+        S = self.site[c]
+        Yx = Y[:, S["l"], :]                                       # (Da, x, s)
+        T = np.einsum("axb,axj->xbj", A[:, S["vd"], :], Yx)
+        G = np.einsum("bxg,xbj->xgj", K[:, S["rho"], :], T) * S["w"][:, None, None]
+        Gu = _segment_sum(G, S["u"], S["Wv"].shape[1])              # (d_u, Dg, s)
+        return np.einsum("vu,ugj->vgj", S["Wv"], Gu)
+
+    # ---- mediating diagram (Fig. 7c,d) --------------------------------------
+    def med_apply(self, c, A, K, X):
+        """(D X)[alpha, rho, j] for the dashed box A_{2c+1} . M_c . K.
+        A: (Da, da'*db', Db); K: (Db, dL, Dg); X: (da, db, Dg, s)."""
+        M = self.med[c]
+        Da = A.shape[0]
+        X1 = np.einsum("al,abgj->lbgj", M["Wdr"], X)
+        out = np.zeros((Da, M["dR"], X.shape[-1]))
+        for rho in range(M["dR"]):
+            X2 = np.einsum("b,lbgj->lgj", M["Wdl"][:, rho], X1)
+            T = np.einsum("blg,lgj->lbj", K, X2)
+            Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"], :]          # (Da, l, Db)
+            out[:, rho, :] = np.einsum("alb,lbj,l->aj", Ar, T, M["Wh"][rho])
+        return out
+
+    def med_applyT(self, c, A, K, Y):
+        """(D^T Y)[a, b, gamma, j];  Y: (Da, dR, s)."""
+        M = self.med[c]
+        Dg, s = K.shape[2], Y.shape[-1]
+        H = np.zeros((M["dL"], M["db"], Dg, s))
+        for rho in range(M["dR"]):
+            Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"], :]          # (Da, l, Db)
+            T = np.einsum("alb,aj->lbj", Ar, Y[:, rho, :])
+            G = np.einsum("blg,lbj,l->lgj", K, T, M["Wh"][rho])
+            H += np.einsum("b,lgj->lbgj", M["Wdl"][:, rho], G)
+        return np.einsum("al,lbgj->abgj", M["Wdr"], H)
+
+
+def trivial_mps(dims):
+    return [np.ones((1, d, 1)) for d in dims]
+
+
+class Options:
+    def __init__(self, chi, width_extra=8, power=1, cut=1e-6, seed=12345):
+        self.chi, self.width_extra, self.power, self.cut, self.seed = chi, width_extra, power, cut, seed
+
+
+def zipper(net, r, psi, opts, truncate=True):
+    """compress(T_r Psi_{r+1}); psi is the left-canonical Psi_{r+1} (list of
+    (Dl, d, Dr) tensors).  Returns (sites of Psi_r, log of the norm factored
+    out)."""
+    ops = RowOps(net, r)
+    C = net.C
+    K = 2 * C - 1
+    dims, split = net.phys_dims(r)
+    chi = opts.chi
+    width = 2 * chi + opts.width_extra
+    conn = np.ones((1, 1, 1))
+    out = [None] * K
+    for k in reversed(range(K)):
+        A = psi[k]
+        Da, Dg = A.shape[0], conn.shape[2]
+        if k % 2 == 0:
+            c = k // 2
+            dm = ops.site[c]["dL"]
+            ds = dims[k]
+            app = lambda Xf, c=c, A=A, K_=conn, ds=ds, Dg=Dg: ops.site_apply(
+                c, A, K_, Xf.reshape(ds, Dg, -1)).reshape(-1, Xf.shape[1])
+            appT = lambda Yf, c=c, A=A, K_=conn, Da=Da, dm=dm: ops.site_applyT(
+                c, A, K_, Yf.reshape(Da, dm, -1)).reshape(-1, Yf.shape[1])
+        else:
+            c = (k - 1) // 2
+            dm = ops.med[c]["dR"]
+            da, db = split[k]
+            ds = da * db
+            # column index sigma = a + da*b: reshape (db, da) then swap to (a, b)
+            app = lambda Xf, c=c, A=A, K_=conn, da=da, db=db, Dg=Dg: ops.med_apply(
+                c, A, K_, Xf.reshape(db, da, Dg, -1).transpose(1, 0, 2, 3)).reshape(-1, Xf.shape[1])
+            appT = lambda Yf, c=c, A=A, K_=conn, Da=Da, dm=dm: ops.med_applyT(
+                c, A, K_, Yf.reshape(Da, dm, -1)).transpose(1, 0, 2, 3).reshape(-1, Yf.shape[1])
+        n_rows, n_cols = Da * dm, ds * Dg
+        t = min(2 * chi, n_rows, n_cols)
+        QU, S, Vt = rsvd(app, appT, n_rows, n_cols, t, width, opts.power, opts.cut,
+                         opts.seed, r, k)
+        out[k] = Vt.reshape(t, ds, Dg)
+        conn = (QU * S[None, :]).reshape(Da, dm, t)
+    scalar = conn.reshape(-1)[0]
+    out[0] = out[0] * np.sign(scalar) if scalar != 0 else out[0]
+    logn = np.log(abs(scalar)) if scalar != 0 else -np.inf
+    if truncate:
+        out, ln2 = truncate_sweep(out, chi, opts.cut)
+        logn += ln2
+    return out, logn
+
+
+def truncate_sweep(sites, chi, cut):
+    """Left-to-right SVD sweep keeping chi singular values per bond; the last
+    site is normalised and its norm returned as a log."""
+    sites = [s.copy() for s in sites]
+    for k in range(len(sites) - 1):
+        Dl, d, Dr = sites[k].shape
+        U, S, Vt = np.linalg.svd(sites[k].reshape(Dl * d, Dr), full_matrices=False)
+        t = min(chi, Dl * d, Dr)
+        S, U, Vt = S[:t].copy(), U[:, :t].copy(), Vt[:t].copy()
+        drop = S <= cut * S[0] if S[0] > 0 else np.ones(t, dtype=bool)
+        S[drop] = 0.0
+        U[:, drop] = 0.0
+        Vt[drop] = 0.0
+        sites[k] = U.reshape(Dl, d, t)
+        sites[k + 1] = np.einsum("tr,rdx->tdx", S[:, None] * Vt, sites[k + 1])
+    nrm = np.linalg.norm(sites[-1])
+    if nrm > 0:
+        sites[-1] = sites[-1] / nrm
+    return sites, (np.log(nrm) if nrm > 0 else -np.inf)
+
+
+class Env:
+    """Boundary MPSs Psi_1 .. Psi_R (Psi_r[k] tensors) and log Z."""
+
+    def __init__(self, psi, lam, logZ, net):
+        self.psi, self.lam, self.logZ, self.net = psi, lam, logZ, net
+
+
+def contract_env(inst, beta, opts):
+    """All boundary MPSs, bottom-up, and log Z (Eq. 10) from the top row."""
+    net = Network(inst, beta)
+    R = net.R
+    psi = {R: trivial_mps(net.phys_dims(R)[0])}
+    lam = {R: 0.0}
+    for r in range(R - 1, 0, -1):
+        sites, ln = zipper(net, r, psi[r + 1], opts)
+        psi[r] = sites
+        lam[r] = lam[r + 1] + ln
+    top, ln0 = zipper(net, 0, psi[1], opts, truncate=False)
+    val = 1.0
+    for s in top:
+        val = val * s.reshape(-1)[0] if s.size == 1 else val * s.sum()
+    logZ = net.shift + lam[1] + ln0 + np.log(abs(val))
+    return Env(psi, lam, logZ, net)

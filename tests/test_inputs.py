@@ -1,0 +1,51 @@
+"""Geometry and instance generators (node counts, locality, planting)."""
+import collections
+
+import numpy as np
+import pytest
+
+from tnb_inputs import make_instance, planted_loops, zephyr_graph, zephyr_cross_cells
+from tnb_inputs.geometry import validate_king, king_lattice
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 6, 12])
+def test_zephyr_counts_and_locality(m):
+    n, e = zephyr_graph(m, 4)
+    assert n == 4 * 4 * m * (2 * m + 1)               # Z_2: 160, Z_12: 4800
+    R, C, cell_of = zephyr_cross_cells(m, 4)
+    assert validate_king(e, R, C, cell_of) == 0
+    sizes = np.bincount(cell_of, minlength=R * C)
+    assert sizes.max() == 16 if m > 1 else sizes.max() == 12
+    deg = np.bincount(e.ravel(), minlength=n)
+    if m >= 4:
+        # the typical Zephyr qubit has 20 neighbours (paper, Sec. II)
+        assert collections.Counter(deg.tolist()).most_common(1)[0][0] == 20
+    assert deg.max() == 20 or m < 3
+
+
+def test_zephyr_edges_are_unique_and_sorted():
+    n, e = zephyr_graph(2, 4)
+    assert np.all(e[:, 0] < e[:, 1])
+    assert len({tuple(x) for x in e.tolist()}) == len(e)
+    assert np.all(np.diff(e[:, 0] * n + e[:, 1]) > 0)
+
+
+def test_king_lattice_locality():
+    (n, e), (R, C, co) = king_lattice(3, 4, a=3)
+    assert n == 9 * 12 and validate_king(e, R, C, co) == 0
+
+
+def test_instance_distributions():
+    inst = make_instance("zephyr", 1000, jdist="uniform", hdist="uniform0.1", m=2, t=4)
+    assert inst.J.min() >= -1 and inst.J.max() <= 1 and abs(inst.J.mean()) < 0.1
+    assert np.abs(inst.h).max() <= 0.1
+    q = make_instance("zephyr", 3000, jdist="quarter", hdist="zero", m=2, t=4)
+    assert set(np.unique(np.abs(q.J) * 4).tolist()) == {1.0, 2.0, 3.0, 4.0}
+    again = make_instance("zephyr", 1000, jdist="uniform", hdist="uniform0.1", m=2, t=4)
+    assert np.array_equal(inst.J, again.J)             # seeded
+
+
+def test_planted_energy_is_sum_of_loop_minima():
+    inst, s, E0 = planted_loops(2, 4, 5000)
+    H = float(np.sum(inst.J * s[inst.edges[:, 0]] * s[inst.edges[:, 1]]))
+    assert H == E0 and E0 < 0
