@@ -1,0 +1,163 @@
+/*
+ * tnbb.h -- C ABI of libtnbb: boundary-MPS conditional marginals and branch
+ * and bound for Ising problems clustered into Potts variables on a king's
+ * lattice, after "Limitations of tensor-network approaches for optimization
+ * and sampling" (Dziubyna, Smierzchalski, Gardas, Rams, Mohseni).
+ *
+ * Conventions shared by every entry point
+ *  - Spins s_i = +-1.  Cluster n = r*cols + c holds the spins with
+ *    cell_of[i] == n in ascending index; bit b of the cluster variable x_n is
+ *    its b-th spin, bit 1 meaning s = +1.
+ *  - Host pointers are read during the call only and copied; device pointers
+ *    (prefix d_) must stay valid until the work queued on `stream` has run.
+ *  - All work is queued on the caller's HIP stream.  Calls that return values
+ *    in host memory synchronise that stream.
+ *  - Every call returns a tnb_status; on failure tnb_last_error() returns a
+ *    message (thread-local, valid until the next call on the thread).  No C++
+ *    exception crosses the ABI.  Handles are owned by the library and freed
+ *    with tnb_destroy.
+ *  - Every floating-point quantity is FP64.
+ */
+#ifndef TNBB_H
+#define TNBB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TNB_OK = 0,
+  TNB_EINVAL = -1,       /* invalid argument (checked before any GPU work)    */
+  TNB_ENOMEM = -2,       /* device or host allocation failed                  */
+  TNB_ENUMERIC = -3,     /* non-finite value, or every marginal of a parent
+                            was non-positive                                  */
+  TNB_EDEVICE = -4,      /* HIP runtime error                                  */
+  TNB_EUNSUPPORTED = -5  /* size beyond what this build supports              */
+} tnb_status;
+
+typedef void* tnb_stream;  /* a hipStream_t; NULL is the null stream */
+
+/* One Ising instance, H(s) = sum_e J_e s_i s_j + sum_i h_i s_i (Eq. 1), all
+ * arrays in host memory.  Edges e have 0 <= edge_i[e] < edge_j[e] < n_spins,
+ * sorted by (i, j), no duplicates.  Every edge must join clusters that are
+ * king's-lattice neighbours (|dr| <= 1 and |dc| <= 1), a cluster holds at
+ * most 24 spins (d <= 2^24, Sec. III), and J, h must be finite. */
+typedef struct {
+  int32_t n_spins;
+  int32_t n_edges;
+  const int32_t* edge_i;
+  const int32_t* edge_j;
+  const double* J;
+  const double* h;
+  int32_t rows;
+  int32_t cols;
+  const int32_t* cell_of;  /* [n_spins], r*cols + c */
+} tnb_instance;
+
+typedef struct tnb_clusters tnb_clusters;
+typedef struct tnb_env tnb_env;
+typedef struct tnb_beam tnb_beam;
+
+/* Eq. (1) for K states.  d_states: device, int8 [K][n_spins] of +-1;
+ * d_E: device, [K].  Couplings are added one after another in edge order,
+ * then the fields in spin order, every operation rounded in FP64 (no fused
+ * multiply-add), so the result is reproducible bit for bit.
+ * Errors: TNB_EINVAL for a malformed instance or K < 0. */
+tnb_status tnb_energies(const tnb_instance* inst, const int8_t* d_states, int64_t K,
+                        double* d_E, tnb_stream stream);
+
+/* Clustered Hamiltonian, Eq. (3)-(5), and Boltzmann weights, Eq. (6).
+ * Builds, on the device, for every cluster n the local energies
+ * E_n[x], x in [0, 2^k_n) (intra-cluster couplings in edge order, then the
+ * fields), the projector masks B_mn (spins of m coupled to neighbour n), the
+ * compressed bond energies Ebar^{mn}[P^{mn} x_m, P^{nm} x_n] (Eq. 4-5), and
+ * weights exp(-beta (E - min E)) for every table; the minima enter a total
+ * log-scale.  beta >= 0.  *out receives a handle owned by the caller.
+ * Errors: TNB_EINVAL (instance, beta), TNB_EUNSUPPORTED (a cluster with more
+ * than 24 spins or a bond table with more than 2^26 entries), TNB_ENOMEM. */
+tnb_status tnb_build_clusters(const tnb_instance* inst, double beta, tnb_stream stream,
+                              tnb_clusters** out);
+
+/* Copy the local-energy table E_n[x] of cluster `cell` (2^k entries) to
+ * d_out (device, n_out doubles).  TNB_EINVAL if n_out != 2^k. */
+tnb_status tnb_cluster_energies(const tnb_clusters* cl, int32_t cell, double* d_out,
+                                int64_t n_out, tnb_stream stream);
+
+/* Copy the bond-energy table Ebar^{mn} (row: P^{mn} x_m, column: P^{nm} x_n)
+ * to d_out; *rows and *cols_out receive its shape.  TNB_EINVAL if m and n are
+ * not coupled neighbours or n_out is too small. */
+tnb_status tnb_bond_energies(const tnb_clusters* cl, int32_t m, int32_t n, double* d_out,
+                             int64_t n_out, int32_t* rows, int32_t* cols_out,
+                             tnb_stream stream);
+
+/* Options of the boundary-MPS compression (Sec. III.C, Fig. 8). */
+typedef struct {
+  int32_t chi;           /* bond dimension of the boundary MPSs, >= 1        */
+  int32_t sketch_extra;  /* oversampling: sketch width is 2*chi + extra      */
+  int32_t power_iters;   /* subspace iterations of the randomized SVD        */
+  double cut;            /* singular values below cut*sigma_max are dropped  */
+  uint64_t seed;         /* Rademacher sketch seed (SplitMix64, counter-based)*/
+} tnb_env_opts;
+
+/* Boundary MPSs Psi_R .. Psi_1 of the lower half-lattice (Fig. 6, 8) and
+ * log Z (Eq. 10).  Psi_r (2*cols-1 sites: a vertical and a two-diagonal
+ * site per column pair) is compress_chi(T_r Psi_{r+1}): a right-to-left
+ * zipper attaching one site or mediating tensor at a time, each dashed box
+ * truncated to 2*chi by a matrix-free randomized SVD, then a left-to-right
+ * SVD sweep to chi.  log_z (host, may be NULL) receives log Z.  The returned
+ * handle keeps a reference to `cl`, which must outlive it.
+ * Errors: TNB_EINVAL (options), TNB_ENUMERIC (zero or non-finite
+ * contraction), TNB_ENOMEM. */
+tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opts, tnb_stream stream,
+                            tnb_env** out, double* log_z);
+
+/* Norm-free diagnostic: number of sites of Psi_r and the shape of site k. */
+tnb_status tnb_env_site_shape(const tnb_env* env, int32_t r, int32_t k, int32_t* dl,
+                              int32_t* d, int32_t* dr);
+
+/* Beam of at most M partial configurations (Sec. III.A), starting with the
+ * single empty configuration at step 0.  The handle references `env`. */
+tnb_status tnb_beam_create(tnb_env* env, int32_t M, tnb_beam** out);
+
+/* Current step n (cluster r*cols + c about to be fixed), number of parents
+ * and the size d of the next cluster; any pointer may be NULL. */
+tnb_status tnb_beam_info(const tnb_beam* beam, int32_t* step, int32_t* n_parents, int32_t* d);
+
+/* Conditional marginals p(x_{n+1} | boundary of parent b) for every parent
+ * of the current step (Eq. 7, 9; Fig. 6b): d_out (device) receives
+ * [n_parents][d] probabilities, normalised per parent, non-positive
+ * contractions clipped to 0.  out_len must be >= n_parents*d.
+ * Errors: TNB_EINVAL (size), TNB_ENUMERIC (a parent with no positive
+ * marginal; it is reported, not dropped, by this call). */
+tnb_status tnb_marginals(tnb_beam* beam, double* d_out, int64_t out_len, tnb_stream stream);
+
+/* One branch-and-bound step (Fig. 3): branch every parent over all d values
+ * of the next cluster, score with the chain rule (Eq. 7) in log space, keep
+ * the most probable candidate of every boundary configuration (Eq. 8; ties
+ * go to the smaller (parent, x)), then the M most probable.  At the last
+ * cluster no merge is done.  p_disc_log (host, may be NULL) receives the log
+ * of the largest probability discarded so far (-inf if none).
+ * TNB_EINVAL when every cluster is already fixed. */
+tnb_status tnb_branch_step(tnb_beam* beam, double* p_disc_log, tnb_stream stream);
+
+/* Export the current partial configurations, best first: d_states (device,
+ * int8 [K][n_spins], unfixed spins 0), d_logp (device, [K], may be NULL);
+ * *count (host) receives min(K, n_parents). */
+tnb_status tnb_beam_export(const tnb_beam* beam, int32_t K, int8_t* d_states, double* d_logp,
+                           int32_t* count, tnb_stream stream);
+
+/* Free a handle from tnb_build_clusters, tnb_contract_env or tnb_beam_create
+ * (free dependants before what they reference).  NULL is ignored. */
+void tnb_destroy(void* handle);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* tnb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNBB_H */

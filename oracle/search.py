@@ -131,7 +131,7 @@ def boundary_key_masks(net, n_fixed):
     return out
 
 
-def solve(inst, beta, env, M, K=8, merge=True):
+def solve(inst, beta, env, M, K=8, merge=True, trace=False):
     """Full search; returns dict with the K lowest states and diagnostics."""
     net = env.net
     R, C = net.R, net.C
@@ -179,7 +179,13 @@ def solve(inst, beta, env, M, K=8, merge=True):
             keep = win[:M]
             if len(win) > M:
                 pd_log = max(pd_log, sc[win[M]])
-            steps.append(dict(n=n, candidates=len(bb), groups=len(win), kept=len(keep)))
+            rec = dict(n=n, candidates=len(bb), groups=len(win), kept=len(keep))
+            if trace:
+                rec["X"] = X[bb[keep]].copy()
+                rec["X"][:, n] = xx[keep]
+                rec["logp"] = sc[keep].copy()
+                rec["p_d_log"] = pd_log
+            steps.append(rec)
             Xn = X[bb[keep]].copy()
             Xn[:, n] = xx[keep]
             Ln = vec[bb[keep], xx[keep]]

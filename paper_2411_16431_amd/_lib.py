@@ -1,0 +1,56 @@
+"""ctypes declarations of include/tnbb.h (argument marshalling only)."""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnbb.so")
+
+c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+P = ctypes.POINTER
+
+
+class TnbInstance(ctypes.Structure):
+    _fields_ = [("n_spins", c_int32), ("n_edges", c_int32),
+                ("edge_i", P(c_int32)), ("edge_j", P(c_int32)),
+                ("J", P(c_double)), ("h", P(c_double)),
+                ("rows", c_int32), ("cols", c_int32), ("cell_of", P(c_int32))]
+
+
+class TnbEnvOpts(ctypes.Structure):
+    _fields_ = [("chi", c_int32), ("sketch_extra", c_int32), ("power_iters", c_int32),
+                ("cut", c_double), ("seed", ctypes.c_uint64)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "tnb_energies": (c_int32, [P(TnbInstance), c_void_p, c_int64, c_void_p, c_void_p]),
+    "tnb_build_clusters": (c_int32, [P(TnbInstance), c_double, c_void_p, P(c_void_p)]),
+    "tnb_cluster_energies": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
+    "tnb_bond_energies": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int64, P(c_int32),
+                                    P(c_int32), c_void_p]),
+    "tnb_contract_env": (c_int32, [c_void_p, P(TnbEnvOpts), c_void_p, P(c_void_p), P(c_double)]),
+    "tnb_env_site_shape": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int32), P(c_int32)]),
+    "tnb_beam_create": (c_int32, [c_void_p, c_int32, P(c_void_p)]),
+    "tnb_beam_info": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),
+    "tnb_marginals": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "tnb_branch_step": (c_int32, [c_void_p, P(c_double), c_void_p]),
+    "tnb_beam_export": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
+    "tnb_destroy": (None, [c_void_p]),
+    "tnb_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtnbb.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback path")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib

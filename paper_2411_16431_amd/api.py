@@ -1,0 +1,206 @@
+"""Python face of libtnbb: numpy/torch arrays in, handles and tensors out.
+
+Device memory comes from torch (the caller's tensors) and work is queued on
+torch's current stream; every computation runs inside libtnbb.
+"""
+import ctypes
+import math
+import re
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+class TnbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libtnbb status %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(code):
+    if code != 0:
+        raise TnbError(code, L.lib().tnb_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def library_path():
+    return L.LIB_PATH
+
+
+def exported_symbols():
+    """Dynamic symbols exported by libtnbb.so whose name starts with tnb_."""
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    return sorted(set(re.findall(r"\b(tnb_[a-z_]+)\b", out)))
+
+
+class HostInstance:
+    """Keeps the host arrays of an instance alive for a C call."""
+
+    def __init__(self, inst):
+        self.ei = np.ascontiguousarray(inst.edges[:, 0], dtype=np.int32)
+        self.ej = np.ascontiguousarray(inst.edges[:, 1], dtype=np.int32)
+        self.J = np.ascontiguousarray(inst.J, dtype=np.float64)
+        self.h = np.ascontiguousarray(inst.h, dtype=np.float64)
+        self.cell = np.ascontiguousarray(inst.cell_of, dtype=np.int32)
+        ip = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+        self.c = L.TnbInstance(int(inst.n_spins), len(self.J), ip(self.ei, ctypes.c_int32),
+                               ip(self.ej, ctypes.c_int32), ip(self.J, ctypes.c_double),
+                               ip(self.h, ctypes.c_double), int(inst.R), int(inst.C),
+                               ip(self.cell, ctypes.c_int32))
+
+
+def energies(inst, states):
+    """Eq. (1) on the device; states: torch int8 cuda tensor [K, N] of +-1."""
+    import torch
+    K = states.shape[0]
+    out = torch.empty(K, dtype=torch.float64, device=states.device)
+    hi = HostInstance(inst)
+    _check(L.lib().tnb_energies(ctypes.byref(hi.c), ctypes.c_void_p(states.data_ptr()), K,
+                                ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+class _Handle:
+    _h = None
+
+    def close(self):
+        if self._h:
+            L.lib().tnb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Clusters(_Handle):
+    """tnb_build_clusters: local tables, projectors, bond tables, weights."""
+
+    def __init__(self, inst, beta):
+        self.inst, self.beta = inst, beta
+        hi = HostInstance(inst)
+        h = ctypes.c_void_p()
+        _check(L.lib().tnb_build_clusters(ctypes.byref(hi.c), float(beta), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def local_energy(self, n):
+        import torch
+        k = int(np.sum(np.asarray(self.inst.cell_of) == n))
+        out = torch.empty(1 << k, dtype=torch.float64, device="cuda")
+        _check(L.lib().tnb_cluster_energies(self._h, n, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                            _stream()))
+        return out
+
+    def bond_energy(self, m, n):
+        import torch
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        code = L.lib().tnb_bond_energies(self._h, m, n, None, 0, ctypes.byref(r), ctypes.byref(c),
+                                         _stream())
+        out = torch.empty(r.value * c.value, dtype=torch.float64, device="cuda")
+        _check(L.lib().tnb_bond_energies(self._h, m, n, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                         ctypes.byref(r), ctypes.byref(c), _stream()))
+        return out.reshape(r.value, c.value)
+
+
+@dataclass
+class EnvOptions:
+    chi: int = 16
+    sketch_extra: int = 8
+    power_iters: int = 2
+    cut: float = 1e-6
+    seed: int = 12345
+
+    def c(self):
+        return L.TnbEnvOpts(self.chi, self.sketch_extra, self.power_iters, self.cut, self.seed)
+
+
+class Env(_Handle):
+    """tnb_contract_env: boundary MPSs and log Z."""
+
+    def __init__(self, clusters, opts):
+        self.clusters = clusters
+        h = ctypes.c_void_p()
+        lz = ctypes.c_double()
+        o = opts.c()
+        _check(L.lib().tnb_contract_env(clusters._h, ctypes.byref(o), _stream(), ctypes.byref(h),
+                                        ctypes.byref(lz)))
+        self._h = h
+        self.logZ = lz.value
+
+    def site_shape(self, r, k):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.lib().tnb_env_site_shape(self._h, r, k, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+
+class Beam(_Handle):
+    """tnb_beam_create / tnb_marginals / tnb_branch_step / tnb_beam_export."""
+
+    def __init__(self, env, M):
+        self.env = env
+        h = ctypes.c_void_p()
+        _check(L.lib().tnb_beam_create(env._h, int(M), ctypes.byref(h)))
+        self._h = h
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.lib().tnb_beam_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def marginals(self):
+        import torch
+        _, npar, d = self.info()
+        out = torch.empty((npar, d), dtype=torch.float64, device="cuda")
+        _check(L.lib().tnb_marginals(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(), _stream()))
+        return out
+
+    def step(self):
+        pd = ctypes.c_double()
+        _check(L.lib().tnb_branch_step(self._h, ctypes.byref(pd), _stream()))
+        return pd.value
+
+    def export(self, K, n_spins):
+        import torch
+        st = torch.empty((K, n_spins), dtype=torch.int8, device="cuda")
+        lp = torch.empty(K, dtype=torch.float64, device="cuda")
+        cnt = ctypes.c_int32()
+        _check(L.lib().tnb_beam_export(self._h, int(K), ctypes.c_void_p(st.data_ptr()),
+                                       ctypes.c_void_p(lp.data_ptr()), ctypes.byref(cnt), _stream()))
+        return st[:cnt.value], lp[:cnt.value]
+
+
+def solve(inst, beta, chi, M, K=8, **env_kw):
+    """Whole pipeline on the device: clusters, boundary MPSs, every beam step,
+    export of the final candidates and their energies; returns the K lowest."""
+    import torch
+    cl = Clusters(inst, beta)
+    env = Env(cl, EnvOptions(chi=chi, **env_kw))
+    beam = Beam(env, M)
+    n_steps = inst.R * inst.C
+    pd = -math.inf
+    for _ in range(n_steps):
+        pd = beam.step()
+    states, logp = beam.export(M, inst.n_spins)
+    E = energies(inst, states)
+    Eh, Sh = E.cpu().numpy(), states.cpu().numpy()
+    order = np.lexsort(tuple(Sh[:, ::-1].T) + (Eh,))
+    seen, keep = set(), []
+    for i in order:
+        key = Sh[i].tobytes()
+        if key not in seen:
+            seen.add(key)
+            keep.append(i)
+        if len(keep) == K:
+            break
+    keep = np.array(keep, dtype=np.int64)
+    return dict(states=Sh[keep], energies=Eh[keep], logZ=env.logZ, p_d_log=pd, env=env, beam=beam)

@@ -1,0 +1,603 @@
+// Boundary-MPS contraction (Sec. III.B-C): row transfer T_r applied to
+// Psi_{r+1} by a right-to-left zipper; each dashed box is compressed by a
+// matrix-free randomized SVD (range finder with a SplitMix64 Rademacher
+// sketch, subspace iterations, Gram-based thin SVD in FP64), then a
+// left-to-right SVD sweep truncates to chi.
+//
+// Diagram kernels (Fig. 7):
+//   site      out[l][a][j]  = sum_{x: P^L x = l} w(x) A[v'(x)] K[rho(x)] Xt[u(x)]
+//   site^T    G[u][g][j]    = sum_{x: P^up x = u} w(x) K[rho(x)]^T A[v'(x)]^T Y[l(x)]
+//   mediating out[rho][a][j] = sum_l Wh(rho,l) A[a'(rho)+da' b'(l)] K[l] X2[l_d(l)][rho_d(rho)]
+//   mediating^T G2[l_d][rho_d] = sum_{rho in rho_d, l in l_d} Wh K[l]^T A[..]^T Y[rho]
+// Each output block is owned by one workgroup (no atomics: deterministic).
+#include <memory>
+
+#include "env.h"
+
+namespace tnb {
+
+std::vector<int> phys_dims(const tnb_clusters* cl, int r) {
+  const Lattice& L = cl->lat;
+  std::vector<int> dims;
+  for (int c = 0; c < L.C; ++c) {
+    dims.push_back(1 << popcount32(cl->B(L.cell(r - 1, c), L.cell(r, c))));
+    if (c + 1 < L.C) {
+      int da = 1 << popcount32(cl->B(L.cell(r - 1, c), L.cell(r, c + 1)));
+      int db = 1 << popcount32(cl->B(L.cell(r - 1, c + 1), L.cell(r, c)));
+      dims.push_back(da * db);
+    }
+  }
+  return dims;
+}
+
+static const double kOne = 1.0;
+
+RowGeom row_geom(const tnb_clusters* cl, int r) {
+  const Lattice& L = cl->lat;
+  RowGeom g;
+  g.r = r;
+  const double* ones = unit_weight();  // 1x1 weight for absent bonds
+  auto view = [&](int m, int n, const double** p, int64_t* sp, int64_t* sq) {
+    if (!cl->weight_view(m, n, p, sp, sq)) { *p = ones; *sp = 0; *sq = 0; }
+  };
+  for (int c = 0; c < L.C; ++c) {
+    RowGeom::Col col;
+    int n = L.cell(r, c);
+    col.n = n;
+    col.up = L.cell(r - 1, c);
+    col.k = L.k[n];
+    col.PL = cl->B(n, L.cell(r - 1, c - 1)) | cl->B(n, L.cell(r, c - 1)) | cl->B(n, L.cell(r + 1, c - 1));
+    col.PR = cl->B(n, L.cell(r - 1, c + 1)) | cl->B(n, L.cell(r, c + 1)) | cl->B(n, L.cell(r + 1, c + 1));
+    col.Bup = cl->B(n, col.up);
+    col.Bdn = cl->B(n, L.cell(r + 1, c));
+    col.dL = 1 << popcount32(col.PL);
+    col.dR = 1 << popcount32(col.PR);
+    col.du = 1 << popcount32(col.Bup);
+    col.dv = 1 << popcount32(cl->B(col.up, n));
+    col.dvd = 1 << popcount32(col.Bdn);
+    col.w = cl->w_loc.p + cl->loc_off[n];
+    view(col.up, n, &col.Wv, &col.Wv_sp, &col.Wv_sq);
+    g.col.push_back(col);
+  }
+  for (int c = 0; c + 1 < L.C; ++c) {
+    RowGeom::Med md;
+    const auto& c0 = g.col[c];
+    const auto& c1 = g.col[c + 1];
+    int n0 = c0.n, n1 = c1.n;
+    int up0 = L.cell(r - 1, c), up1 = L.cell(r - 1, c + 1);
+    int dn0 = L.cell(r + 1, c), dn1 = L.cell(r + 1, c + 1);
+    md.dR = c0.dR;
+    md.dL = c1.dL;
+    md.da = 1 << popcount32(cl->B(up0, n1));
+    md.db = 1 << popcount32(cl->B(up1, n0));
+    md.da2 = 1 << popcount32(cl->B(n0, dn1));
+    md.db2 = 1 << popcount32(cl->B(n1, dn0));
+    md.pos_h_rho = pext_host(cl->B(n0, n1), c0.PR);
+    md.pos_h_ell = pext_host(cl->B(n1, n0), c1.PL);
+    md.pos_d_rho = pext_host(cl->B(n0, up1), c0.PR);
+    md.pos_d_ell = pext_host(cl->B(n1, up0), c1.PL);
+    md.pos_a2 = pext_host(cl->B(n0, dn1), c0.PR);
+    md.pos_b2 = pext_host(cl->B(n1, dn0), c1.PL);
+    md.drd = 1 << popcount32(md.pos_d_rho);
+    md.dld = 1 << popcount32(md.pos_d_ell);
+    view(n0, n1, &md.Wh, &md.Wh_sp, &md.Wh_sq);
+    view(up0, n1, &md.Wdr, &md.Wdr_sp, &md.Wdr_sq);
+    view(up1, n0, &md.Wdl, &md.Wdl_sp, &md.Wdl_sq);
+    g.med.push_back(md);
+  }
+  return g;
+}
+
+// ------------------------------------------------------------------ kernels
+__device__ __forceinline__ uint64_t splitmix64_dev(uint64_t c) {
+  uint64_t z = (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void rademacher_kernel(double* __restrict__ O, int64_t n, int s, uint64_t key) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  O[idx] = (splitmix64_dev(key + uint64_t(idx)) >> 63) ? 1.0 : -1.0;
+}
+
+__global__ void identity_kernel(double* __restrict__ O, int64_t n) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  O[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+}
+
+// out[l] (Da x s) for l = blockIdx.x.  T = K[rho] Xt[u] is staged in LDS.
+__global__ void site_apply_kernel(int k, uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
+                                  uint32_t Bup, uint32_t Bdn, const double* __restrict__ w,
+                                  const double* __restrict__ A, int Da, int Db,
+                                  const double* __restrict__ Kc, int Dg,
+                                  const double* __restrict__ Xt, int s, double* __restrict__ out) {
+  extern __shared__ double T[];  // Db x s
+  const uint32_t l = blockIdx.x;
+  double* o = out + size_t(l) * Da * s;
+  for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) o[idx] = 0.0;
+  for (int f = 0; f < nfree; ++f) {
+    const uint32_t x = pdep_dev(l, PL) | pdep_dev(uint32_t(f), FREE);
+    const double wx = w[x];
+    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;
+    const double* Xu = Xt + size_t(pext_dev(x, Bup)) * Dg * s;
+    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
+      const int b = idx / s, j = idx % s;
+      double acc = 0.0;
+      for (int g = 0; g < Dg; ++g) acc = fma(Kr[b * Dg + g], Xu[g * s + j], acc);
+      T[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) {
+      const int a = idx / s, j = idx % s;
+      double acc = 0.0;
+      for (int b = 0; b < Db; ++b) acc = fma(Av[a * Db + b], T[b * s + j], acc);
+      o[idx] = fma(wx, acc, o[idx]);
+    }
+  }
+}
+
+// G[u] (Dg x s) for u = blockIdx.x.
+__global__ void site_applyT_kernel(int k, uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL,
+                                   uint32_t PR, uint32_t Bdn, const double* __restrict__ w,
+                                   const double* __restrict__ A, int Da, int Db,
+                                   const double* __restrict__ Kc, int Dg,
+                                   const double* __restrict__ Y, int s, double* __restrict__ G) {
+  extern __shared__ double T[];  // Db x s
+  const uint32_t u = blockIdx.x;
+  double* o = G + size_t(u) * Dg * s;
+  for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) o[idx] = 0.0;
+  for (int f = 0; f < nfree; ++f) {
+    const uint32_t x = pdep_dev(u, Bup) | pdep_dev(uint32_t(f), FREE);
+    const double wx = w[x];
+    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;
+    const double* Yl = Y + size_t(pext_dev(x, PL)) * Da * s;
+    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
+      const int b = idx / s, j = idx % s;
+      double acc = 0.0;
+      for (int a = 0; a < Da; ++a) acc = fma(Av[a * Db + b], Yl[a * s + j], acc);
+      T[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) {
+      const int g = idx / s, j = idx % s;
+      double acc = 0.0;
+      for (int b = 0; b < Db; ++b) acc = fma(Kr[b * Dg + g], T[b * s + j], acc);
+      o[idx] = fma(wx, acc, o[idx]);
+    }
+  }
+}
+
+// out[rho] (Da x s) for rho = blockIdx.x; X2: [l_d][rho_d][Dg][s].
+__global__ void med_apply_kernel(RowGeom::Med md, const double* __restrict__ A, int Da, int Db,
+                                 const double* __restrict__ Kc, int Dg,
+                                 const double* __restrict__ X2, int s, double* __restrict__ out) {
+  extern __shared__ double T[];  // Db x s
+  const uint32_t rho = blockIdx.x;
+  double* o = out + size_t(rho) * Da * s;
+  for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) o[idx] = 0.0;
+  const uint32_t rd = pext_dev(rho, md.pos_d_rho), a2 = pext_dev(rho, md.pos_a2);
+  const uint32_t hr = pext_dev(rho, md.pos_h_rho);
+  for (int l = 0; l < md.dL; ++l) {
+    const uint32_t ld = pext_dev(uint32_t(l), md.pos_d_ell), b2 = pext_dev(uint32_t(l), md.pos_b2);
+    const double wh = md.Wh[hr * md.Wh_sp + pext_dev(uint32_t(l), md.pos_h_ell) * md.Wh_sq];
+    const double* Kr = Kc + size_t(l) * Db * Dg;
+    const double* Xs = X2 + (size_t(ld) * md.drd + rd) * Dg * s;
+    const double* Av = A + size_t(a2 + md.da2 * b2) * Da * Db;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
+      const int b = idx / s, j = idx % s;
+      double acc = 0.0;
+      for (int g = 0; g < Dg; ++g) acc = fma(Kr[b * Dg + g], Xs[g * s + j], acc);
+      T[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) {
+      const int a = idx / s, j = idx % s;
+      double acc = 0.0;
+      for (int b = 0; b < Db; ++b) acc = fma(Av[a * Db + b], T[b * s + j], acc);
+      o[idx] = fma(wh, acc, o[idx]);
+    }
+  }
+}
+
+// G2[l_d][rho_d] (Dg x s), block = (l_d, rho_d).
+__global__ void med_applyT_kernel(RowGeom::Med md, const double* __restrict__ A, int Da, int Db,
+                                  const double* __restrict__ Kc, int Dg,
+                                  const double* __restrict__ Y, int s, double* __restrict__ G2) {
+  extern __shared__ double T[];  // Db x s
+  const uint32_t ld = blockIdx.x / md.drd, rd = blockIdx.x % md.drd;
+  double* o = G2 + size_t(blockIdx.x) * Dg * s;
+  for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) o[idx] = 0.0;
+  const uint32_t freeR = uint32_t(md.dR - 1) & ~md.pos_d_rho;
+  const uint32_t freeL = uint32_t(md.dL - 1) & ~md.pos_d_ell;
+  const int nR = md.dR / md.drd, nL = md.dL / md.dld;
+  for (int fr = 0; fr < nR; ++fr) {
+    const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(uint32_t(fr), freeR);
+    const uint32_t a2 = pext_dev(rho, md.pos_a2), hr = pext_dev(rho, md.pos_h_rho);
+    const double* Yr = Y + size_t(rho) * Da * s;
+    for (int fl = 0; fl < nL; ++fl) {
+      const uint32_t l = pdep_dev(ld, md.pos_d_ell) | pdep_dev(uint32_t(fl), freeL);
+      const uint32_t b2 = pext_dev(l, md.pos_b2);
+      const double wh = md.Wh[hr * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+      const double* Kr = Kc + size_t(l) * Db * Dg;
+      const double* Av = A + size_t(a2 + md.da2 * b2) * Da * Db;
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
+        const int b = idx / s, j = idx % s;
+        double acc = 0.0;
+        for (int a = 0; a < Da; ++a) acc = fma(Av[a * Db + b], Yr[a * s + j], acc);
+        T[idx] = acc;
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) {
+        const int g = idx / s, j = idx % s;
+        double acc = 0.0;
+        for (int b = 0; b < Db; ++b) acc = fma(Kr[b * Dg + g], T[b * s + j], acc);
+        o[idx] = fma(wh, acc, o[idx]);
+      }
+    }
+  }
+}
+
+// site[sigma][i][g] = V[(sigma*Dg + g)][i]   (V: n_cols x t)
+__global__ void vb_to_site_kernel(const double* __restrict__ V, int ds, int Dg, int t,
+                                  double* __restrict__ site) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(ds) * Dg * t) return;
+  const int sg = int(idx / (int64_t(t) * Dg)), rem = int(idx % (int64_t(t) * Dg));
+  const int i = rem / Dg, g = rem % Dg;
+  site[idx] = V[(int64_t(sg) * Dg + g) * t + i];
+}
+
+// W[row][i] = VT[i][row] * S[i]  (s x t)
+__global__ void scale_vt_kernel(const double* __restrict__ VT, const double* __restrict__ S, int s,
+                                int t, double* __restrict__ W) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= s * t) return;
+  const int row = idx / t, i = idx % t;
+  W[idx] = VT[i * s + row] * S[i];
+}
+
+// SVT[i][b] = S[i] * VT[i][b]
+__global__ void scale_rows_kernel(const double* __restrict__ VT, const double* __restrict__ S, int t,
+                                  int m, double* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= t * m) return;
+  out[idx] = S[idx / m] * VT[idx];
+}
+
+__global__ void sumsq_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc = fma(x[i], x[i], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void scale_kernel(double* __restrict__ x, int64_t n, double a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= a;
+}
+
+__global__ void fill_kernel(double* __restrict__ x, int64_t n, double v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+static unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+// -------------------------------------------------------------- the zipper
+struct Zipper {
+  const tnb_clusters* cl;
+  const tnb_env_opts& o;
+  la::Scratch& ws;
+  hipStream_t st;
+  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, SVT;
+
+  // D X for site k of row geometry g; X: (ds*Dg) x s, out: (dm*Da) x s
+  void apply(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
+             double* out) {
+    const int Da = A.dl, Db = A.dr;
+    if (k % 2 == 0) {
+      const auto& c = g.col[k / 2];
+      // Xt[u] = sum_v W(v,u) X[v]: (du x Dg*s) = W^T (du x dv) . X (dv x Dg*s)
+      double* Xt = X1.p;
+      la::gemm(1, c.du, Dg * s, c.dv, la::View{c.Wv, c.Wv_sq, c.Wv_sp, 0}, la::View{X, Dg * s, 1, 0},
+               Xt, int64_t(Dg) * s, 0, 1.0, 0.0, ws, st);
+      const uint32_t full = c.k ? ((c.k == 32) ? ~0u : ((1u << c.k) - 1u)) : 0u;
+      const uint32_t FREE = full & ~c.PL;
+      const int nfree = 1 << popcount32(FREE);
+      hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
+                         k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
+                         conn.p, Dg, Xt, s, out);
+      HIPC(hipGetLastError());
+    } else {
+      const auto& md = g.med[(k - 1) / 2];
+      // X1[b] (dld x Dg*s) = Wdr^T . X[b]  with X[(b*da + a)][Dg*s]
+      la::gemm(md.db, md.dld, Dg * s, md.da, la::View{md.Wdr, md.Wdr_sq, md.Wdr_sp, 0},
+               la::View{X, int64_t(Dg) * s, 1, int64_t(md.da) * Dg * s}, X1.p, int64_t(Dg) * s,
+               int64_t(md.dld) * Dg * s, 1.0, 0.0, ws, st);
+      // X2[ld] (drd x Dg*s) = Wdl^T (drd x db) . X1[:, ld] (db x Dg*s)
+      la::gemm(md.dld, md.drd, Dg * s, md.db, la::View{md.Wdl, md.Wdl_sq, md.Wdl_sp, 0},
+               la::View{X1.p, int64_t(md.dld) * Dg * s, 1, int64_t(Dg) * s}, X2.p,
+               int64_t(Dg) * s, int64_t(md.drd) * Dg * s, 1.0, 0.0, ws, st);
+      hipLaunchKernelGGL(med_apply_kernel, dim3(md.dR), dim3(256), size_t(Db) * s * sizeof(double), st,
+                         md, A.data.p, Da, Db, conn.p, Dg, X2.p, s, out);
+      HIPC(hipGetLastError());
+    }
+  }
+
+  // D^T Y; Y: (dm*Da) x s, out: (ds*Dg) x s
+  void applyT(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* Yin, int s,
+              double* out) {
+    const int Da = A.dl, Db = A.dr;
+    if (k % 2 == 0) {
+      const auto& c = g.col[k / 2];
+      const uint32_t full = c.k ? ((1u << c.k) - 1u) : 0u;
+      const uint32_t FREE = full & ~c.Bup;
+      const int nfree = 1 << popcount32(FREE);
+      double* G = X1.p;  // du x Dg x s
+      hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
+                         k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg,
+                         Yin, s, G);
+      HIPC(hipGetLastError());
+      // out[v] = sum_u W(v,u) G[u]
+      la::gemm(1, c.dv, Dg * s, c.du, la::View{c.Wv, c.Wv_sp, c.Wv_sq, 0}, la::View{G, Dg * s, 1, 0},
+               out, int64_t(Dg) * s, 0, 1.0, 0.0, ws, st);
+    } else {
+      const auto& md = g.med[(k - 1) / 2];
+      double* G2 = X2.p;  // [ld][rd][Dg*s]
+      hipLaunchKernelGGL(med_applyT_kernel, dim3(md.dld * md.drd), dim3(256),
+                         size_t(Db) * s * sizeof(double), st, md, A.data.p, Da, Db, conn.p, Dg, Yin,
+                         s, G2);
+      HIPC(hipGetLastError());
+      // H[ld] (db x Dg*s) = Wdl (db x drd) . G2[ld]
+      la::gemm(md.dld, md.db, Dg * s, md.drd, la::View{md.Wdl, md.Wdl_sp, md.Wdl_sq, 0},
+               la::View{G2, int64_t(Dg) * s, 1, int64_t(md.drd) * Dg * s}, X1.p, int64_t(Dg) * s,
+               int64_t(md.db) * Dg * s, 1.0, 0.0, ws, st);
+      // out[b] (da x Dg*s) = Wdr (da x dld) . H[:, b]
+      la::gemm(md.db, md.da, Dg * s, md.dld, la::View{md.Wdr, md.Wdr_sp, md.Wdr_sq, 0},
+               la::View{X1.p, int64_t(md.db) * Dg * s, 1, int64_t(Dg) * s}, out, int64_t(Dg) * s,
+               int64_t(md.da) * Dg * s, 1.0, 0.0, ws, st);
+    }
+  }
+
+  static void ensure(DevBuf<double>& b, size_t n) {
+    if (b.n < n) b.alloc(n + n / 4 + 64);
+  }
+
+  // compress(T_r psi) -> out (2C-1 sites), returns log of the factored norm
+  double run(int r, const Mps& below, Mps& outm, bool truncate) {
+    const RowGeom g = row_geom(cl, r);
+    const std::vector<int> dims = phys_dims(cl, r);
+    const int K = int(dims.size());
+    const int chi = o.chi;
+    const int width = 2 * chi + o.sketch_extra;
+    outm.sites.clear();
+    outm.sites.resize(K);
+    ensure(conn, 1);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, conn.p, int64_t(1), 1.0);
+    int Dg = 1, dmk = 1;  // right bond of the new MPS, MPO bond right of site k
+    for (int k = K - 1; k >= 0; --k) {
+      const Site& A = below.sites[k];
+      const int Da = A.dl;
+      int dm;
+      if (k % 2 == 0) dm = g.col[k / 2].dL;
+      else dm = g.med[(k - 1) / 2].dR;
+      (void)dmk;
+      const int ds = dims[k];
+      const int64_t n_rows = int64_t(dm) * Da, n_cols = int64_t(ds) * Dg;
+      const int t = int(std::min<int64_t>({int64_t(2) * chi, n_rows, n_cols}));
+      const bool sketch = n_cols > width;
+      const int s = sketch ? width : int(n_cols);
+      if (size_t(A.dr) * s * sizeof(double) > 65536)
+        fail(TNB_EUNSUPPORTED, "diagram tile exceeds 64 KiB of LDS (bond x sketch width too large)");
+      // work sizes
+      size_t x1n = 0, x2n = 0;
+      if (k % 2 == 0) {
+        const auto& c = g.col[k / 2];
+        x1n = std::max<size_t>(size_t(c.du) * Dg * s, 1);
+      } else {
+        const auto& md = g.med[(k - 1) / 2];
+        x1n = std::max(size_t(md.db) * md.dld * Dg * s, size_t(md.dld) * md.db * Dg * s);
+        x2n = size_t(md.dld) * md.drd * Dg * s;
+        if (double(md.dR) * md.dL > double(1 << 26))
+          fail(TNB_EUNSUPPORTED, "mediating diagram with more than 2^26 (rho, l) pairs");
+      }
+      ensure(X1, x1n);
+      ensure(X2, std::max<size_t>(x2n, 1));
+      ensure(Om, size_t(n_cols) * s);
+      ensure(Y, size_t(n_rows) * s);
+      ensure(Qb, size_t(std::max(n_rows, n_cols)) * s);
+      ensure(Z, size_t(n_cols) * s);
+      ensure(Bt, size_t(n_cols) * s);
+      if (sketch) {
+        const uint64_t key = splitmix64_host((uint64_t(o.seed) << 24) + (uint64_t(r) << 12) + uint64_t(k));
+        hipLaunchKernelGGL(rademacher_kernel, dim3(blocks(n_cols * s)), dim3(256), 0, st, Om.p, n_cols, s, key);
+      } else {
+        hipLaunchKernelGGL(identity_kernel, dim3(blocks(n_cols * n_cols)), dim3(256), 0, st, Om.p, n_cols);
+      }
+      apply(g, k, A, Dg, dm, Om.p, s, Y.p);
+      if (sketch) {
+        for (int it = 0; it < o.power_iters; ++it) {
+          la::orth(Y.p, n_rows, s, o.cut, Qb.p, ws, st);
+          applyT(g, k, A, Dg, dm, Qb.p, s, Z.p);
+          la::orth(Z.p, n_cols, s, o.cut, Qb.p, ws, st);
+          apply(g, k, A, Dg, dm, Qb.p, s, Y.p);
+        }
+      }
+      la::orth(Y.p, n_rows, s, o.cut, Qb.p, ws, st);
+      applyT(g, k, A, Dg, dm, Qb.p, s, Bt.p);
+      // B = Bt^T (s x n_cols): thin SVD through Bt (n_cols x s)
+      ensure(Vb, size_t(n_cols) * t);
+      ensure(S, size_t(t));
+      ensure(VT, size_t(t) * s);
+      la::thin_svd_tall(Bt.p, n_cols, s, t, o.cut, Vb.p, S.p, VT.p, ws, st);
+      Site& ns = outm.sites[k];
+      ns.dl = t;
+      ns.d = ds;
+      ns.dr = Dg;
+      ns.data.alloc(ns.size());
+      hipLaunchKernelGGL(vb_to_site_kernel, dim3(blocks(int64_t(ds) * Dg * t)), dim3(256), 0, st, Vb.p,
+                         ds, Dg, t, ns.data.p);
+      // connector (dm*Da x t) = Q (n_rows x s) . (U_B S) (s x t)
+      ensure(Wc, size_t(s) * t);
+      hipLaunchKernelGGL(scale_vt_kernel, dim3(blocks(int64_t(s) * t)), dim3(256), 0, st, VT.p, S.p, s, t, Wc.p);
+      ensure(conn_next, size_t(n_rows) * t);
+      la::gemm(1, int(n_rows), t, s, la::View{Qb.p, s, 1, 0}, la::View{Wc.p, t, 1, 0}, conn_next.p, t, 0,
+               1.0, 0.0, ws, st);
+      std::swap(conn, conn_next);
+      Dg = t;
+      dmk = dm;
+      HIPC(hipGetLastError());
+    }
+    // conn is 1x1: the factored scalar
+    double scalar = 0.0;
+    HIPC(hipMemcpyAsync(&scalar, conn.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (!std::isfinite(scalar)) fail(TNB_ENUMERIC, "non-finite value in the row transfer of row " + std::to_string(r));
+    if (scalar == 0.0) fail(TNB_ENUMERIC, "row transfer of row " + std::to_string(r) + " vanished");
+    if (scalar < 0.0)
+      hipLaunchKernelGGL(scale_kernel, dim3(blocks(int64_t(outm.sites[0].size()))), dim3(256), 0, st,
+                         outm.sites[0].data.p, int64_t(outm.sites[0].size()), -1.0);
+    double logn = std::log(std::fabs(scalar));
+    if (truncate) logn += sweep(outm);
+    return logn;
+  }
+
+  static uint64_t splitmix64_host(uint64_t c) {
+    uint64_t z = (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+
+  // left-to-right SVD truncation to chi; normalises the last site
+  double sweep(Mps& m) {
+    const int K = int(m.sites.size());
+    const int chi = o.chi;
+    for (int k = 0; k + 1 < K; ++k) {
+      Site& a = m.sites[k];
+      Site& b = m.sites[k + 1];
+      const int64_t n = int64_t(a.d) * a.dl;
+      const int mm = a.dr;
+      const int t = int(std::min<int64_t>({int64_t(chi), n, int64_t(mm)}));
+      ensure(Vb, size_t(n) * t);
+      ensure(S, size_t(t));
+      ensure(VT, size_t(t) * mm);
+      la::thin_svd_tall(a.data.p, n, mm, t, o.cut, Vb.p, S.p, VT.p, ws, st);
+      Site na;
+      na.dl = a.dl;
+      na.d = a.d;
+      na.dr = t;
+      na.data.alloc(na.size());
+      HIPC(hipMemcpyAsync(na.data.p, Vb.p, na.size() * sizeof(double), hipMemcpyDeviceToDevice, st));
+      ensure(SVT, size_t(t) * mm);
+      hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks(int64_t(t) * mm)), dim3(256), 0, st, VT.p, S.p, t, mm, SVT.p);
+      Site nb;
+      nb.dl = t;
+      nb.d = b.d;
+      nb.dr = b.dr;
+      nb.data.alloc(nb.size());
+      la::gemm(b.d, t, b.dr, mm, la::View{SVT.p, mm, 1, 0},
+               la::View{b.data.p, b.dr, 1, int64_t(b.dl) * b.dr}, nb.data.p, b.dr,
+               int64_t(t) * b.dr, 1.0, 0.0, ws, st);
+      a = std::move(na);
+      b = std::move(nb);
+    }
+    Site& last = m.sites[K - 1];
+    ensure(S, 1);
+    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, st, last.data.p, int64_t(last.size()), S.p);
+    double ss = 0.0;
+    HIPC(hipMemcpyAsync(&ss, S.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (!(ss > 0.0) || !std::isfinite(ss)) fail(TNB_ENUMERIC, "boundary MPS vanished in truncation");
+    const double nrm = std::sqrt(ss);
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks(int64_t(last.size()))), dim3(256), 0, st, last.data.p,
+                       int64_t(last.size()), 1.0 / nrm);
+    return std::log(nrm);
+  }
+};
+
+}  // namespace tnb
+
+using namespace tnb;
+
+extern "C" tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opts, tnb_stream stream,
+                                       tnb_env** out, double* log_z) {
+  return guarded([&] {
+    if (!out) fail(TNB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
+    if (!opts || opts->chi < 1 || opts->chi > 64 || opts->sketch_extra < 0 || opts->sketch_extra > 64 ||
+        opts->power_iters < 0 || opts->power_iters > 8 || !(opts->cut >= 0.0) || !(opts->cut < 1.0))
+      fail(TNB_EINVAL, "options out of range (1 <= chi <= 64, 0 <= extra <= 64, 0 <= power <= 8, 0 <= cut < 1)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto env = std::make_unique<tnb_env>();
+    env->cl = cl;
+    env->opts = *opts;
+    const int R = cl->lat.R;
+    env->psi.resize(R + 1);
+    // Psi_R = 1
+    {
+      std::vector<int> dims = phys_dims(cl, R);
+      Mps& m = env->psi[R];
+      m.sites.resize(dims.size());
+      for (size_t k = 0; k < dims.size(); ++k) {
+        Site& s = m.sites[k];
+        s.dl = 1;
+        s.d = dims[k];
+        s.dr = 1;
+        s.data.alloc(s.size());
+        hipLaunchKernelGGL(fill_kernel, dim3(blocks(int64_t(s.size()))), dim3(256), 0, st, s.data.p,
+                           int64_t(s.size()), 1.0);
+      }
+      m.logscale = 0.0;
+    }
+    Zipper z{cl, env->opts, env->ws, st};
+    for (int r = R - 1; r >= 1; --r) {
+      double ln = z.run(r, env->psi[r + 1], env->psi[r], true);
+      env->psi[r].logscale = env->psi[r + 1].logscale + ln;
+    }
+    Mps top;
+    double ln0 = z.run(0, env->psi[1], top, false);
+    double val = 1.0;
+    for (auto& s : top.sites) {
+      if (s.size() != 1) fail(TNB_EDEVICE, "top row contraction did not reduce to a scalar");
+      double v = 0.0;
+      HIPC(hipMemcpyAsync(&v, s.data.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      val *= v;
+    }
+    if (!(val != 0.0) || !std::isfinite(val)) fail(TNB_ENUMERIC, "partition function vanished");
+    env->logZ = cl->shift + env->psi[1].logscale + ln0 + std::log(std::fabs(val));
+    if (log_z) *log_z = env->logZ;
+    HIPC(hipStreamSynchronize(st));
+    *out = env.release();
+  });
+}
+
+extern "C" tnb_status tnb_env_site_shape(const tnb_env* env, int32_t r, int32_t k, int32_t* dl, int32_t* d,
+                                         int32_t* dr) {
+  return guarded([&] {
+    if (!env || env->kind != KIND_ENV) fail(TNB_EINVAL, "not an env handle");
+    if (r < 1 || r >= int(env->psi.size())) fail(TNB_EINVAL, "r out of range");
+    const auto& m = env->psi[r];
+    if (k < 0 || k >= int(m.sites.size())) fail(TNB_EINVAL, "k out of range");
+    if (dl) *dl = m.sites[k].dl;
+    if (d) *d = m.sites[k].d;
+    if (dr) *dr = m.sites[k].dr;
+  });
+}

@@ -1,0 +1,49 @@
+// FP64 dense linear algebra used by the compression: strided batched GEMM,
+// symmetric eigendecomposition (cyclic Jacobi, one workgroup) and the
+// Gram-based orthonormalisation / thin SVD built on them.
+#pragma once
+#include "common.h"
+
+namespace tnb {
+namespace la {
+
+// Element (i, j) of batch b lives at p[b*bs + i*rs + j*cs].
+struct View {
+  const double* p;
+  int64_t rs, cs, bs;
+};
+
+// Reusable device scratch (grows, never shrinks).
+struct Scratch {
+  DevBuf<double> buf[6];
+  double* get(int slot, size_t n) {
+    if (buf[slot].n < n) buf[slot].alloc(n + n / 4 + 64);
+    return buf[slot].p;
+  }
+};
+
+// C[b] (M x N, row-major with leading dimension ldc, batch stride bsc)
+//   = alpha * A[b] (M x K) . B[b] (K x N) + beta * C[b].
+// Deterministic: K is split into fixed chunks whose partial products are
+// summed in chunk order.
+void gemm(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t ldc, int64_t bsc,
+          double alpha, double beta, Scratch& ws, hipStream_t s);
+
+// Symmetric eigendecomposition of G (s x s, row-major, overwritten):
+// lam[i] descending, V[:, i] (row-major s x s) the eigenvectors.
+void eigh(double* G, int s, double* V, double* lam, hipStream_t st);
+
+// Orthonormal basis of the numerical range of Y (n x s, row-major): Q (n x s)
+// holds the directions with singular value > cut * largest, remaining
+// columns zero.  Two Gram passes (the second re-orthonormalises).
+void orth(const double* Y, int64_t n, int s, double cut, double* Q, Scratch& ws, hipStream_t st);
+
+// Thin SVD through the Gram matrix of a tall M (n x m): keeps t = min(tmax, m)
+// singular triplets, dropping sigma <= cut * sigma_max (set to 0).
+//   U  (n x t) = M V S^-1 (zero columns for dropped)   [if U != nullptr]
+//   S  (t), VT (t x m) = V^T rows.
+void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double* U, double* S,
+                   double* VT, Scratch& ws, hipStream_t st);
+
+}  // namespace la
+}  // namespace tnb

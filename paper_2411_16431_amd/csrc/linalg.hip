@@ -1,0 +1,267 @@
+#include "linalg.h"
+
+namespace tnb {
+namespace la {
+
+constexpr int TILE = 16;
+
+// One 16x16 output tile per block, K range [k0, k1) of the chunk blockIdx.z.
+__global__ void gemm_kernel(int M, int N, int64_t K, int64_t kchunk, const double* __restrict__ A,
+                            int64_t ars, int64_t acs, int64_t abs_, const double* __restrict__ B,
+                            int64_t brs, int64_t bcs, int64_t bbs, double* __restrict__ P,
+                            int64_t pbs_chunk, int64_t pbs_batch, int nb) {
+  __shared__ double As[TILE][TILE + 1];
+  __shared__ double Bs[TILE][TILE + 1];
+  const int ntj = (N + TILE - 1) / TILE;
+  const int ti = int(blockIdx.x / ntj), tj = int(blockIdx.x % ntj);
+  const int b = int(blockIdx.y) % nb;
+  const int chunk = int(blockIdx.y) / nb;
+  const int i = ti * TILE + threadIdx.y;
+  const int j = tj * TILE + threadIdx.x;
+  const int64_t k0 = int64_t(chunk) * kchunk;
+  const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+  const double* Ab = A + b * abs_;
+  const double* Bb = B + b * bbs;
+  double acc = 0.0;
+  for (int64_t kt = k0; kt < k1; kt += TILE) {
+    const int64_t ka = kt + threadIdx.x, kb = kt + threadIdx.y;
+    const int ia = ti * TILE + threadIdx.y;
+    const int jb = tj * TILE + threadIdx.x;
+    As[threadIdx.y][threadIdx.x] = (ia < M && ka < k1) ? Ab[ia * ars + ka * acs] : 0.0;
+    Bs[threadIdx.y][threadIdx.x] = (kb < k1 && jb < N) ? Bb[kb * brs + jb * bcs] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TILE; ++kk) acc = fma(As[threadIdx.y][kk], Bs[kk][threadIdx.x], acc);
+    __syncthreads();
+  }
+  if (i < M && j < N) P[chunk * pbs_chunk + b * pbs_batch + int64_t(i) * N + j] = acc;
+}
+
+__global__ void gemm_finish_kernel(int nb, int M, int N, int nchunk, const double* __restrict__ P,
+                                   int64_t pbs_chunk, int64_t pbs_batch, double* __restrict__ C,
+                                   int64_t ldc, int64_t bsc, double alpha, double beta) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = int64_t(M) * N;
+  if (idx >= per * nb) return;
+  const int b = int(idx / per);
+  const int i = int((idx % per) / N), j = int(idx % N);
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += P[c * pbs_chunk + b * pbs_batch + int64_t(i) * N + j];
+  double* dst = C + b * bsc + int64_t(i) * ldc + j;
+  *dst = beta == 0.0 ? alpha * acc : alpha * acc + beta * *dst;
+}
+
+static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t ldc,
+                      int64_t bsc, double alpha, double beta, Scratch& ws, hipStream_t s) {
+  const int64_t tiles2d = int64_t((M + TILE - 1) / TILE) * ((N + TILE - 1) / TILE);
+  const int64_t tiles = tiles2d * batch;
+  int64_t nchunk = 1;
+  if (K > 2048 && tiles < 1024) {
+    nchunk = (K + 2047) / 2048;
+    int64_t cap = (4096 + tiles - 1) / tiles;
+    if (nchunk > cap) nchunk = cap;
+    if (nchunk * batch > 65535) nchunk = 65535 / batch;
+    if (nchunk < 1) nchunk = 1;
+  }
+  const int64_t kchunk = K > 0 ? (K + nchunk - 1) / nchunk : 0;
+  const int64_t per = int64_t(M) * N;
+  double* P = ws.get(5, size_t(per * batch * nchunk));
+  dim3 grid(unsigned(tiles2d), unsigned(batch * nchunk));
+  hipLaunchKernelGGL(gemm_kernel, grid, dim3(TILE, TILE), 0, s, M, N, K, kchunk, A.p, A.rs, A.cs,
+                     A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
+  HIPC(hipGetLastError());
+  const int64_t tot = per * batch;
+  hipLaunchKernelGGL(gemm_finish_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, batch,
+                     M, N, int(nchunk), P, per * batch, per, C, ldc, bsc, alpha, beta);
+  HIPC(hipGetLastError());
+}
+
+void gemm(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t ldc, int64_t bsc,
+          double alpha, double beta, Scratch& ws, hipStream_t s) {
+  if (batch <= 0 || M <= 0 || N <= 0) return;
+  const int maxb = 32768;
+  for (int b0 = 0; b0 < batch; b0 += maxb) {
+    const int nb = batch - b0 < maxb ? batch - b0 : maxb;
+    View a{A.p + A.bs * b0, A.rs, A.cs, A.bs}, bb{B.p + B.bs * b0, B.rs, B.cs, B.bs};
+    gemm_part(nb, M, N, K, a, bb, C + bsc * b0, ldc, bsc, alpha, beta, ws, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi (Golub & Van Loan, Sec. 8.5) with the round-robin ordering:
+// each round applies up to s/2 disjoint rotations at once.
+__global__ void __launch_bounds__(1024) jacobi_kernel(double* __restrict__ G, int s,
+                                                      double* __restrict__ V,
+                                                      double* __restrict__ lam) {
+  extern __shared__ double sh[];
+  double* cs = sh;                 // [m/2] cosines
+  double* sn = sh + 512;           // [m/2] sines
+  int* pp = reinterpret_cast<int*>(sh + 1024);
+  int* qq = pp + 512;
+  double* red = sh + 1536;         // [1024]
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = s + (s & 1);       // even number of players (one dummy if odd)
+  for (int idx = tid; idx < s * s; idx += nt) V[idx] = (idx / s == idx % s) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int idx = tid; idx < s * s; idx += nt) {
+      double g = G[idx];
+      tot += g * g;
+      if (idx / s != idx % s) off += g * g;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    off = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    tot = red[0];
+    __syncthreads();
+    if (!(off > 1e-30 * tot) || tot == 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      // pair list of this round: player 0 fixed, others rotate
+      for (int a = tid; a < m / 2; a += nt) {
+        int p1 = (a == 0) ? 0 : 1 + (a - 1 + round) % (m - 1);
+        int p2 = 1 + (m - 2 - a + round) % (m - 1);
+        int p = p1 < p2 ? p1 : p2, q = p1 < p2 ? p2 : p1;
+        double c = 1.0, sv = 0.0;
+        if (q < s) {
+          double apq = G[p * s + q];
+          if (apq != 0.0) {
+            double tau = (G[q * s + q] - G[p * s + p]) / (2.0 * apq);
+            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sv = t * c;
+          }
+        }
+        pp[a] = p;
+        qq[a] = q;
+        cs[a] = c;
+        sn[a] = sv;
+      }
+      __syncthreads();
+      // rows: G <- J^T G
+      for (int idx = tid; idx < (m / 2) * s; idx += nt) {
+        int a = idx / s, k = idx % s;
+        int p = pp[a], q = qq[a];
+        if (q >= s || sn[a] == 0.0) continue;
+        double gp = G[p * s + k], gq = G[q * s + k];
+        G[p * s + k] = cs[a] * gp - sn[a] * gq;
+        G[q * s + k] = sn[a] * gp + cs[a] * gq;
+      }
+      __syncthreads();
+      // columns: G <- G J ; V <- V J
+      for (int idx = tid; idx < (m / 2) * s; idx += nt) {
+        int a = idx / s, k = idx % s;
+        int p = pp[a], q = qq[a];
+        if (q >= s || sn[a] == 0.0) continue;
+        double gp = G[k * s + p], gq = G[k * s + q];
+        G[k * s + p] = cs[a] * gp - sn[a] * gq;
+        G[k * s + q] = sn[a] * gp + cs[a] * gq;
+        double vp = V[k * s + p], vq = V[k * s + q];
+        V[k * s + p] = cs[a] * vp - sn[a] * vq;
+        V[k * s + q] = sn[a] * vp + cs[a] * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // sort eigenpairs by descending eigenvalue (ties by index): rank scatter
+  double* d = red;  // reuse: diagonal
+  for (int i = tid; i < s; i += nt) d[i] = G[i * s + i];
+  __syncthreads();
+  int* rank = reinterpret_cast<int*>(cs);
+  for (int i = tid; i < s; i += nt) {
+    int r = 0;
+    for (int j = 0; j < s; ++j) r += (d[j] > d[i]) || (d[j] == d[i] && j < i);
+    rank[i] = r;
+  }
+  __syncthreads();
+  for (int i = tid; i < s; i += nt) lam[rank[i]] = d[i];
+  // permute V columns in place through G as temporary
+  for (int idx = tid; idx < s * s; idx += nt) G[idx] = V[idx];
+  __syncthreads();
+  for (int idx = tid; idx < s * s; idx += nt) {
+    int row = idx / s, col = idx % s;
+    V[row * s + rank[col]] = G[idx];
+  }
+}
+
+void eigh(double* G, int s, double* V, double* lam, hipStream_t st) {
+  if (s <= 0) return;
+  if (s > 1000) fail(TNB_EUNSUPPORTED, "eigensolver limited to 1000 x 1000");
+  size_t shm = 2560 * sizeof(double);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), shm, st, G, s, V, lam);
+  HIPC(hipGetLastError());
+}
+
+// W (s x s) = V[:, keep] * diag(1/sqrt(lam)) for lam > thr * lam0, else 0.
+__global__ void inv_sqrt_weights_kernel(const double* __restrict__ V, const double* __restrict__ lam,
+                                        int s, double rel, double* __restrict__ W) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= s * s) return;
+  const int col = idx % s;
+  const double l0 = lam[0], l = lam[col];
+  W[idx] = (l0 > 0.0 && l > rel * l0) ? V[idx] / sqrt(l) : 0.0;
+}
+
+void orth(const double* Y, int64_t n, int s, double cut, double* Q, Scratch& ws, hipStream_t st) {
+  double* G = ws.get(0, size_t(s) * s);
+  double* V = ws.get(1, size_t(s) * s);
+  double* lam = ws.get(2, size_t(s));
+  double* W = ws.get(3, size_t(s) * s);
+  double* T = ws.get(4, size_t(n) * s);
+  // pass 1: Q1 = Y V L^-1/2 over the kept directions
+  gemm(1, s, s, n, View{Y, 1, s, 0}, View{Y, s, 1, 0}, G, s, 0, 1.0, 0.0, ws, st);
+  eigh(G, s, V, lam, st);
+  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((s * s + 255) / 256), dim3(256), 0, st, V, lam, s,
+                     cut * cut, W);
+  gemm(1, int(n), s, s, View{Y, s, 1, 0}, View{W, s, 1, 0}, T, s, 0, 1.0, 0.0, ws, st);
+  // pass 2: re-orthonormalise (eigenvalues ~1 for kept, 0 for padding)
+  gemm(1, s, s, n, View{T, 1, s, 0}, View{T, s, 1, 0}, G, s, 0, 1.0, 0.0, ws, st);
+  eigh(G, s, V, lam, st);
+  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((s * s + 255) / 256), dim3(256), 0, st, V, lam, s,
+                     0.25, W);
+  gemm(1, int(n), s, s, View{T, s, 1, 0}, View{W, s, 1, 0}, Q, s, 0, 1.0, 0.0, ws, st);
+}
+
+// S[i] = sqrt(lam[i]) (0 if dropped), Winv = V[:, :t] / S (0 if dropped),
+// VT = V[:, :t]^T (zero rows if dropped).
+__global__ void svd_factors_kernel(const double* __restrict__ V, const double* __restrict__ lam,
+                                   int m, int t, double rel, double* __restrict__ S,
+                                   double* __restrict__ Winv, double* __restrict__ VT) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * t) return;
+  const int row = idx / t, col = idx % t;
+  const double l0 = lam[0], l = lam[col];
+  const bool keep = l0 > 0.0 && l > rel * l0;
+  const double sig = keep ? sqrt(l) : 0.0;
+  if (row == 0) S[col] = sig;
+  Winv[idx] = keep ? V[row * m + col] / sig : 0.0;
+  if (VT) VT[col * m + row] = keep ? V[row * m + col] : 0.0;
+}
+
+void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double* U, double* S,
+                   double* VT, Scratch& ws, hipStream_t st) {
+  double* G = ws.get(0, size_t(m) * m);
+  double* V = ws.get(1, size_t(m) * m);
+  double* lam = ws.get(2, size_t(m));
+  double* Winv = ws.get(3, size_t(m) * t);
+  gemm(1, m, m, n, View{M, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  eigh(G, m, V, lam, st);
+  hipLaunchKernelGGL(svd_factors_kernel, dim3((m * t + 255) / 256), dim3(256), 0, st, V, lam, m, t,
+                     cut * cut, S, Winv, VT);
+  HIPC(hipGetLastError());
+  if (U) gemm(1, int(n), t, m, View{M, m, 1, 0}, View{Winv, t, 1, 0}, U, t, 0, 1.0, 0.0, ws, st);
+}
+
+}  // namespace la
+}  // namespace tnb

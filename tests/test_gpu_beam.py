@@ -1,0 +1,81 @@
+"""Parity of the HIP marginals and branch-and-bound steps with the oracle."""
+import numpy as np
+import pytest
+
+from tnb_inputs import make_instance, planted_loops
+from oracle import ising
+from oracle.bmps import contract_env, Options, Network
+from oracle.search import solve, right_envs, marginals
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_16431_amd as pk
+    return pk, torch
+
+
+CASES = [("king", dict(R=2, C=3, a=2), 64, 16), ("king", dict(R=3, C=4, a=1), 64, 8),
+         ("zephyr", dict(m=1, t=2), 64, 32), ("king", dict(R=4, C=4, a=2), 4, 16),
+         ("zephyr", dict(m=2, t=1), 4, 24)]
+
+
+@pytest.mark.parametrize("kind,kw,chi,M", CASES)
+def test_stepwise_beam_matches_oracle(kind, kw, chi, M):
+    pk, torch = _gpu()
+    beta = 1.0
+    inst = make_instance(kind, 301, jdist="uniform", hdist="uniform0.1", **kw)
+    ora_env = contract_env(inst, beta, Options(chi=chi, power=2, seed=5))
+    ref = solve(inst, beta, ora_env, M=M, K=4, trace=True)
+    cl = pk.Clusters(inst, beta)
+    env = pk.Env(cl, pk.EnvOptions(chi=chi, power_iters=2, seed=5))
+    beam = pk.Beam(env, M)
+    from oracle.potts import Potts
+    P = Potts(inst)
+    for rec in ref["steps"]:
+        if rec["n"] == 0:
+            p = beam.marginals().cpu().numpy()
+            net = ora_env.net
+            X0 = np.zeros((1, net.R * net.C), dtype=np.int64)
+            R0 = right_envs(net, ora_env, 0, X0)
+            q, _ = marginals(net, ora_env, 0, 0, X0, np.ones((1, 1)), R0[0])
+            assert np.allclose(p[0], q[0] / q[0].sum(), rtol=1e-5, atol=1e-12)
+        pd = beam.step()
+        states, logp = beam.export(M, inst.n_spins)
+        S = states.cpu().numpy()
+        got_X = P.cluster_of_states(np.where(S == 0, -1, S))[:, : rec["n"] + 1]
+        assert got_X.shape[0] == rec["X"].shape[0]
+        assert np.array_equal(got_X, rec["X"][:, : rec["n"] + 1]), "beam differs at step %d" % rec["n"]
+        assert np.allclose(logp.cpu().numpy(), rec["logp"], rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("kind,kw", [("king", dict(R=3, C=3, a=1)), ("king", dict(R=2, C=2, a=2))])
+def test_exact_search_finds_ground_state(kind, kw):
+    pk, torch = _gpu()
+    inst = make_instance(kind, 302, jdist="uniform", hdist="uniform0.1", **kw)
+    res = pk.solve(inst, 2.0, chi=64, M=4096, K=2, cut=1e-13)
+    bf = ising.brute_force(inst, 2.0)
+    assert abs(res["energies"][0] - bf["E_min"]) < 1e-12
+    assert np.array_equal(res["energies"], ising.energies(inst, res["states"]))
+
+
+def test_planted_instance():
+    pk, torch = _gpu()
+    inst, s, E0 = planted_loops(1, 2, 77, loops_per_cell=2)
+    res = pk.solve(inst, 1.0, chi=32, M=256, K=2)
+    assert abs(res["energies"][0] - E0) < 1e-12
+
+
+def test_marginals_sum_to_one():
+    pk, torch = _gpu()
+    inst = make_instance("zephyr", 303, jdist="uniform", hdist="uniform0.1", m=2, t=1)
+    cl = pk.Clusters(inst, 1.0)
+    env = pk.Env(cl, pk.EnvOptions(chi=4))
+    beam = pk.Beam(env, 8)
+    for _ in range(6):
+        p = beam.marginals().cpu().numpy()
+        assert np.allclose(p.sum(axis=1), 1.0, atol=1e-12) and (p >= 0).all()
+        beam.step()
