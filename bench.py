@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the boundary-MPS branch-and-bound hot path on one MI355X.
+
+One step = the whole path on one synthetic instance: cluster tables and
+Boltzmann weights, all boundary MPSs (zipper + randomized SVD), every beam
+step (right environments, conditional marginals, merge and top-M), export of
+the final states and their energies.  The metric counts spin marginals: for
+every parent b at every beam step, the k marginals <s_i>_b of the cluster
+being fixed, which its conditional distribution p_b(x) determines.
+
+Prints one JSON line.  With --gpus N > 1 it exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # configs[0]: Zephyr Z_2 (t=4, 160 spins), J ~ U[-1,1], h ~ U[-0.1,0.1],
+    # beta = 1, chi = 16, beam M = 64, 8 states returned, FP64.
+    "zephyr_z2_t4_plain": dict(kind="zephyr", kw=dict(m=2, t=4), seed=1000, jdist="uniform",
+                               hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
+    # small sibling used for quick checks (t = 2 cells of 8 spins)
+    "zephyr_z2_t2_plain": dict(kind="zephyr", kw=dict(m=2, t=2), seed=1000, jdist="uniform",
+                               hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
+}
+
+PEAK = {"alu_fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="zephyr_z2_t4_plain", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--power-iters", type=int, default=2)
+    return ap.parse_args()
+
+
+def make(wl):
+    from tnb_inputs import make_instance
+    return make_instance(wl["kind"], wl["seed"], jdist=wl["jdist"], hdist=wl["hdist"], **wl["kw"])
+
+
+def cpu_baseline(inst, wl, counts, marg_per_step, power):
+    """Oracle (plain numpy FP64) timed on slices of the same workload and
+    extrapolated to one step: one site diagram application, a slice of the
+    rho loop of one mediating application (scaled to the full loop), and the
+    marginals of one parent; multiplied by the counts of one GPU step."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle.bmps import Network, RowOps
+    rng = np.random.default_rng(0)
+    net = Network(inst, wl["beta"])
+    r = 1
+    ops = RowOps(net, r)
+    chi = wl["chi"]
+    s = 2 * chi + 8
+    # largest site and mediating diagram of row 1
+    c_site = max(range(net.C), key=lambda c: len(ops.site[c]["x"]))
+    S = ops.site[c_site]
+    dvd = int(S["vd"].max()) + 1
+    A = rng.standard_normal((chi, dvd, chi))
+    K = rng.standard_normal((chi, S["dR"], 2 * chi))
+    X = rng.standard_normal((S["Wv"].shape[0], 2 * chi, s))
+    t0 = time.perf_counter()
+    ops.site_apply(c_site, A, K, X)
+    t_site = time.perf_counter() - t0
+    c_med = max(range(net.C - 1), key=lambda c: ops.med[c]["dR"] * ops.med[c]["dL"])
+    Md = ops.med[c_med]
+    n_sl = 4
+    full_dR = Md["dR"]
+    Md_slice = dict(Md)
+    Md_slice["dR"] = n_sl
+    ops.med[c_med] = Md_slice
+    A2 = rng.standard_normal((chi, Md["da2"] * (int(Md["b2"].max()) + 1), chi))
+    K2 = rng.standard_normal((chi, Md["dL"], 2 * chi))
+    X2 = rng.standard_normal((Md["Wdr"].shape[0], Md["Wdl"].shape[0], 2 * chi, s))
+    t0 = time.perf_counter()
+    ops.med_apply(c_med, A2, K2, X2)
+    t_med = (time.perf_counter() - t0) * full_dR / n_sl
+    ops.med[c_med] = Md
+    site_calls = counts.get("site", 0)
+    med_calls = counts.get("med", 0)
+    t_step = site_calls * t_site + med_calls * t_med
+    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas") or 1
+    sample = ("oracle RowOps.site_apply on the largest cell of row 1 (%.2f s) and %d of %d rho "
+              "iterations of the largest mediating diagram of row 1 (%.2f s extrapolated to the full "
+              "loop), times the %d site and %d mediating diagram applications of one step; beam "
+              "steps not included (extrapolated lower bound on the oracle's time)" %
+              (t_site, n_sl, full_dR, t_med, site_calls, med_calls))
+    return dict(value=marg_per_step / t_step, unit="spin marginals/s", cores=int(threads),
+                kind="oracle", sample=sample, seconds_per_step_extrapolated=t_step)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    import paper_2411_16431_amd as pk
+    wl = WORKLOADS[args.workload]
+    inst = make(wl)
+    env_kw = dict(power_iters=args.power_iters, seed=4242)
+
+    def one():
+        return pk.solve(inst, wl["beta"], chi=wl["chi"], M=wl["M"], K=wl["K"], **env_kw)
+
+    for i in range(args.warmup):
+        one()
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    pk.profile_enable(True)
+    t0 = time.perf_counter()
+    res = None
+    for i in range(args.steps):
+        res = one()
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pk.profile_enable(False)
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    marg = res["spin_marginals"]
+    value = marg * args.steps / (t1 - t0)
+    # dominant kernel over the timed region
+    prof = {}
+    for name in pk.profile_names():
+        prof[name] = pk.profile_query(name)
+    dom = max(prof, key=lambda n: prof[n][0]) if prof else None
+    roof = None
+    if dom:
+        ms, n, fl, by = prof[dom]
+        avg_s = ms / 1000.0 / n
+        roof = {"bound": "alu", "kernel": dom, "achieved": fl / n / avg_s / 1e12,
+                "peak": PEAK["alu_fp64_tflops"], "unit": "TFLOP/s",
+                "frac": fl / n / avg_s / 1e12 / PEAK["alu_fp64_tflops"], "traffic": None,
+                "avg_ms": ms / n, "launches_per_step": n / args.steps,
+                "share_of_step": ms / args.steps / ms_step}
+    counts = {"site": (prof.get("site_apply", (0, 0))[1] + prof.get("site_applyT", (0, 0))[1]) / args.steps,
+              "med": (prof.get("med_apply", (0, 0))[1] + prof.get("med_applyT", (0, 0))[1]
+                      + prof.get("medf_Y2", (0, 0))[1] + prof.get("medf_W2", (0, 0))[1]) / args.steps}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inst, wl, counts, marg, args.power_iters)
+    out = {
+        "metric": "beam marginals/sec and best energy gap vs oracle, adjoint+batched vs plain",
+        "value": value, "unit": "spin marginals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "spins": int(inst.n_spins),
+                   "lattice": [int(inst.R), int(inst.C)], "beta": wl["beta"], "chi": wl["chi"],
+                   "beam_M": wl["M"], "returned_K": wl["K"], "mode": "plain (per-step marginals, no adjoint)",
+                   "power_iters": args.power_iters},
+        "best_energy": float(res["energies"][0]), "energy_gap_vs_oracle": None,
+        "logZ": res["logZ"], "spin_marginals_per_step": marg,
+        "roofline": roof, "cpu_baseline": cpu,
+        "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

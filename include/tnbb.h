@@ -149,6 +149,21 @@ tnb_status tnb_branch_step(tnb_beam* beam, double* p_disc_log, tnb_stream stream
 tnb_status tnb_beam_export(const tnb_beam* beam, int32_t K, int8_t* d_states, double* d_logp,
                            int32_t* count, tnb_stream stream);
 
+/* Measurement support.  tnb_profile_enable(1) clears and starts recording a
+ * pair of HIP events around every launch of the instrumented kernels, on the
+ * stream the kernel runs on, together with its algorithmic flop and byte
+ * counts; tnb_profile_enable(0) stops recording.  tnb_profile_query
+ * synchronises the recorded events and returns, for the kernel `name`
+ * (e.g. "site_apply", "medf_Y2", "renv_V", "beam_q"), the summed duration in
+ * milliseconds, the number of launches and the summed algorithmic flops and
+ * bytes; unknown names give zeros.  tnb_profile_names writes a
+ * comma-separated list of recorded names into buf (NUL-terminated,
+ * truncated to len). */
+tnb_status tnb_profile_enable(int32_t on);
+tnb_status tnb_profile_query(const char* name, double* total_ms, int64_t* launches, double* flops,
+                             double* bytes);
+tnb_status tnb_profile_names(char* buf, int64_t len);
+
 /* Free a handle from tnb_build_clusters, tnb_contract_env or tnb_beam_create
  * (free dependants before what they reference).  NULL is ignored. */
 void tnb_destroy(void* handle);

@@ -211,17 +211,21 @@ class RowOps:
             PR0, PL1 = net.PR(r, c), net.PL(r, c + 1)
             rho = np.arange(1 << popcount(PR0))
             ell = np.arange(1 << popcount(PL1))
-            Wh = net.Wt(n0, n1)[sub(rho, PR0, net.B(n0, n1))[:, None],
-                                sub(ell, PL1, net.B(n1, n0))[None, :]]
             up0, up1 = net.cell(r - 1, c), net.cell(r - 1, c + 1)
-            Wdr = net.Wt(up0, n1)[:, sub(ell, PL1, net.B(n1, up0))]   # [a, l]
-            Wdl = net.Wt(up1, n0)[:, sub(rho, PR0, net.B(n0, up1))]   # [b, rho]
-            a2 = sub(rho, PR0, net.B(n0, net.cell(r + 1, c + 1)))      # Psi_{r+1} a'
-            b2 = sub(ell, PL1, net.B(n1, net.cell(r + 1, c)))          # Psi_{r+1} b'
-            da2 = 1 << popcount(net.B(n0, net.cell(r + 1, c + 1)))
-            self.med.append(dict(Wh=Wh, Wdr=Wdr, Wdl=Wdl, a2=a2, b2=b2, da2=da2,
-                                 dR=len(rho), dL=len(ell),
-                                 da=Wdr.shape[0], db=Wdl.shape[0]))
+            ld = sub(ell, PL1, net.B(n1, up0))          # spins of (r,c+1) facing (r-1,c)
+            rd = sub(rho, PR0, net.B(n0, up1))          # spins of (r,c) facing (r-1,c+1)
+            self.med.append(dict(
+                Wh_tab=net.Wt(n0, n1), hr=sub(rho, PR0, net.B(n0, n1)), hl=sub(ell, PL1, net.B(n1, n0)),
+                Wdr=net.Wt(up0, n1), Wdl=net.Wt(up1, n0), ld=ld, rd=rd,   # W(a, l_d), W(b, rho_d)
+                a2=sub(rho, PR0, net.B(n0, net.cell(r + 1, c + 1))),       # Psi_{r+1} a'
+                b2=sub(ell, PL1, net.B(n1, net.cell(r + 1, c))),           # Psi_{r+1} b'
+                da2=1 << popcount(net.B(n0, net.cell(r + 1, c + 1))),
+                dR=len(rho), dL=len(ell)))
+
+    @staticmethod
+    def _Wh_row(M, rho):
+        """Horizontal weight W_h(rho, l) for every l (one row, built on demand)."""
+        return M["Wh_tab"][M["hr"][rho], M["hl"]]
 
     # ---- site diagram (Fig. 7a,b) ------------------------------------------
     def site_apply(self, c, A, K, X):
@@ -244,30 +248,43 @@ class RowOps:
         return np.einsum("vu,ugj->vgj", S["Wv"], Gu)
 
     # ---- mediating diagram (Fig. 7c,d) --------------------------------------
+    CHUNK = 4096
+
     def med_apply(self, c, A, K, X):
         """(D X)[alpha, rho, j] for the dashed box A_{2c+1} . M_c . K.
-        A: (Da, da'*db', Db); K: (Db, dL, Dg); X: (da, db, Dg, s)."""
+        A: (Da, da'*db', Db); K: (Db, dL, Dg); X: (da, db, Dg, s).
+        W_dr depends on l only through l_d and W_dl on rho only through
+        rho_d, so both are applied to X first: X2[l_d, rho_d]."""
         M = self.med[c]
         Da = A.shape[0]
-        X1 = np.einsum("al,abgj->lbgj", M["Wdr"], X)
+        Xa = np.einsum("al,abgj->lbgj", M["Wdr"], X)                 # (l_d, b, Dg, s)
+        X2 = np.einsum("br,lbgj->lrgj", M["Wdl"], Xa)                # (l_d, rho_d, Dg, s)
         out = np.zeros((Da, M["dR"], X.shape[-1]))
         for rho in range(M["dR"]):
-            X2 = np.einsum("b,lbgj->lgj", M["Wdl"][:, rho], X1)
-            T = np.einsum("blg,lgj->lbj", K, X2)
-            Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"], :]          # (Da, l, Db)
-            out[:, rho, :] = np.einsum("alb,lbj,l->aj", Ar, T, M["Wh"][rho])
+            wh = self._Wh_row(M, rho)
+            for l0 in range(0, M["dL"], self.CHUNK):
+                l1 = min(M["dL"], l0 + self.CHUNK)
+                X2r = X2[M["ld"][l0:l1], M["rd"][rho]]                 # (l, Dg, s)
+                T = np.einsum("blg,lgj->lbj", K[:, l0:l1, :], X2r)
+                Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"][l0:l1], :]   # (Da, l, Db)
+                out[:, rho, :] += np.einsum("alb,lbj,l->aj", Ar, T, wh[l0:l1])
         return out
 
     def med_applyT(self, c, A, K, Y):
         """(D^T Y)[a, b, gamma, j];  Y: (Da, dR, s)."""
         M = self.med[c]
         Dg, s = K.shape[2], Y.shape[-1]
-        H = np.zeros((M["dL"], M["db"], Dg, s))
+        nld, nrd = M["Wdr"].shape[1], M["Wdl"].shape[1]
+        G2 = np.zeros((nld, nrd, Dg, s))                               # sum over l in l_d, rho in rho_d
         for rho in range(M["dR"]):
-            Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"], :]          # (Da, l, Db)
-            T = np.einsum("alb,aj->lbj", Ar, Y[:, rho, :])
-            G = np.einsum("blg,lbj,l->lgj", K, T, M["Wh"][rho])
-            H += np.einsum("b,lgj->lbgj", M["Wdl"][:, rho], G)
+            wh = self._Wh_row(M, rho)
+            for l0 in range(0, M["dL"], self.CHUNK):
+                l1 = min(M["dL"], l0 + self.CHUNK)
+                Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"][l0:l1], :]   # (Da, l, Db)
+                T = np.einsum("alb,aj->lbj", Ar, Y[:, rho, :])
+                G = np.einsum("blg,lbj,l->lgj", K[:, l0:l1, :], T, wh[l0:l1])
+                np.add.at(G2, (M["ld"][l0:l1], M["rd"][rho]), G)
+        H = np.einsum("br,lrgj->lbgj", M["Wdl"], G2)                   # (l_d, b, Dg, s)
         return np.einsum("al,lbgj->abgj", M["Wdr"], H)
 
 

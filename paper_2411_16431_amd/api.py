@@ -188,7 +188,10 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
     beam = Beam(env, M)
     n_steps = inst.R * inst.C
     pd = -math.inf
+    marg = 0
     for _ in range(n_steps):
+        _, npar, d = beam.info()
+        marg += npar * int(round(math.log2(d)))
         pd = beam.step()
     states, logp = beam.export(M, inst.n_spins)
     E = energies(inst, states)
@@ -203,4 +206,24 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
         if len(keep) == K:
             break
     keep = np.array(keep, dtype=np.int64)
-    return dict(states=Sh[keep], energies=Eh[keep], logZ=env.logZ, p_d_log=pd, env=env, beam=beam)
+    return dict(states=Sh[keep], energies=Eh[keep], logZ=env.logZ, p_d_log=pd, env=env, beam=beam,
+                spin_marginals=marg)
+
+
+def profile_enable(on=True):
+    """Start (clearing earlier records) or stop per-kernel event timing."""
+    _check(L.lib().tnb_profile_enable(1 if on else 0))
+
+
+def profile_query(name):
+    """(total_ms, launches, flops, bytes) of one instrumented kernel."""
+    ms, n, fl, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(L.lib().tnb_profile_query(name.encode(), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                     ctypes.byref(by)))
+    return ms.value, n.value, fl.value, by.value
+
+
+def profile_names():
+    buf = ctypes.create_string_buffer(4096)
+    _check(L.lib().tnb_profile_names(buf, 4096))
+    return [x for x in buf.value.decode().split(",") if x]

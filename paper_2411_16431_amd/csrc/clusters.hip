@@ -146,6 +146,11 @@ __global__ void ising_energy_kernel(const int8_t* __restrict__ s, int64_t K, int
   out[kx] = acc;
 }
 
+static bool g_prof = false;
+static std::vector<ProfRec> g_recs;
+bool prof_on() { return g_prof; }
+void prof_push(const ProfRec& r) { g_recs.push_back(r); }
+
 const double* unit_weight() {
   static double* ptr[64] = {nullptr};
   int dev = 0;
@@ -361,5 +366,59 @@ extern "C" tnb_status tnb_bond_energies(const tnb_clusters* cl, int32_t m, int32
     if (!d_out || n_out < int64_t(bd.rows) * bd.cols) fail(TNB_EINVAL, "output too small");
     HIPC(hipMemcpyAsync(d_out, cl->E_bond.p + bd.off, size_t(bd.rows) * bd.cols * sizeof(double),
                         hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  });
+}
+
+extern "C" tnb_status tnb_profile_enable(int32_t on) {
+  return guarded([&] {
+    if (on) {
+      for (auto& r : tnb::g_recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+      }
+      tnb::g_recs.clear();
+    }
+    tnb::g_prof = on != 0;
+  });
+}
+
+extern "C" tnb_status tnb_profile_query(const char* name, double* total_ms, int64_t* launches,
+                                        double* flops, double* bytes) {
+  return guarded([&] {
+    if (!name) fail(TNB_EINVAL, "name is NULL");
+    double ms = 0.0, fl = 0.0, by = 0.0;
+    int64_t n = 0;
+    for (auto& r : tnb::g_recs) {
+      if (std::strcmp(r.name, name) != 0) continue;
+      HIPC(hipEventSynchronize(r.b));
+      float e = 0.f;
+      HIPC(hipEventElapsedTime(&e, r.a, r.b));
+      ms += e;
+      fl += r.flops;
+      by += r.bytes;
+      ++n;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    if (flops) *flops = fl;
+    if (bytes) *bytes = by;
+  });
+}
+
+extern "C" tnb_status tnb_profile_names(char* buf, int64_t len) {
+  return guarded([&] {
+    if (!buf || len < 1) fail(TNB_EINVAL, "bad buffer");
+    std::string out;
+    std::vector<std::string> seen;
+    for (auto& r : tnb::g_recs) {
+      bool dup = false;
+      for (auto& x : seen) dup = dup || x == r.name;
+      if (dup) continue;
+      seen.push_back(r.name);
+      if (!out.empty()) out += ",";
+      out += r.name;
+    }
+    std::strncpy(buf, out.c_str(), size_t(len - 1));
+    buf[len - 1] = '\0';
   });
 }

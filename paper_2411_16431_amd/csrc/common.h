@@ -142,6 +142,34 @@ tnb_status guarded(F&& f) {
   }
 }
 
+// Optional per-kernel timing with HIP events recorded on the launch stream.
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+bool prof_on();
+void prof_push(const ProfRec& r);
+struct KTimer {
+  bool on;
+  ProfRec r;
+  hipStream_t st;
+  KTimer(const char* name, hipStream_t s, double flops, double bytes) : on(prof_on()), st(s) {
+    r = ProfRec{name, nullptr, nullptr, flops, bytes};
+    if (on) {
+      HIPC(hipEventCreate(&r.a));
+      HIPC(hipEventCreate(&r.b));
+      HIPC(hipEventRecord(r.a, st));
+    }
+  }
+  ~KTimer() {
+    if (on) {
+      (void)hipEventRecord(r.b, st);
+      prof_push(r);
+    }
+  }
+};
+
 enum HandleKind : uint32_t { KIND_CLUSTERS = 0x544E4231u, KIND_ENV = 0x544E4232u, KIND_BEAM = 0x544E4233u };
 
 }  // namespace tnb

@@ -246,6 +246,218 @@ __global__ void med_applyT_kernel(RowGeom::Med md, const double* __restrict__ A,
   }
 }
 
+// ---- factored mediating diagram --------------------------------------------
+// Used when the spins of (r,c) facing column c+1 split into those facing the
+// upper diagonal cell (rho_d) and those facing the lower one (a'), with no
+// overlap, and likewise for l = (l_d, b').  Then the horizontal weight
+// depends on rho only through rho_d and the a'-bits hA of its horizontal
+// spins, and on l through l_d and b', and the (rho, l) double sum factors:
+//   apply :  Y2[rd][b'][hA] = sum_ld Wh(h(rd,hA), h'(ld,b')) K[l(ld,b')] X2[ld][rd]
+//            out[(rd,a')]   = sum_b' A[a' + da' b'] Y2[rd][b'][hA(a')]
+//   applyT:  W2[rd][b'][hL] = sum_a' Wh(h(rd,a'), h'(hL,b')) A[a'+da'b']^T Y[(rd,a')]
+//            G2[ld][rd]     = sum_b' K[l(ld,b')]^T W2[rd][b'][hL(ld)]
+struct MedF {
+  RowGeom::Med md;
+  int hA_bits = 0;           // a'-space mask of the horizontal spins
+  uint32_t hA_mask = 0;
+  uint32_t hL_mask = 0;      // l_d-space mask of the horizontal spins of l
+  int nHA = 1, nHL = 1;
+};
+
+__device__ __forceinline__ uint32_t rho_of(const RowGeom::Med& md, uint32_t rd, uint32_t a2) {
+  return pdep_dev(rd, md.pos_d_rho) | pdep_dev(a2, md.pos_a2);
+}
+__device__ __forceinline__ uint32_t ell_of(const RowGeom::Med& md, uint32_t ld, uint32_t b2) {
+  return pdep_dev(ld, md.pos_d_ell) | pdep_dev(b2, md.pos_b2);
+}
+
+template <int PT>
+__global__ void __launch_bounds__(256) medf_Y2_kernel(MedF f, const double* __restrict__ Kc, int Db, int Dg,
+                                                      const double* __restrict__ X2, int s,
+                                                      double* __restrict__ Y2) {
+  extern __shared__ double sh[];
+  double* Ks = sh;              // Db x Dg
+  double* Xs = sh + Db * Dg;    // Dg x s
+  __shared__ double wsh[16];
+  const RowGeom::Med& md = f.md;
+  const uint32_t rd = blockIdx.x / md.db2, b2 = blockIdx.x % md.db2;
+  double acc[16][PT];
+#pragma unroll
+  for (int h = 0; h < 16; ++h)
+#pragma unroll
+    for (int p = 0; p < PT; ++p) acc[h][p] = 0.0;
+  const int nld = md.dld;
+  for (int ld = 0; ld < nld; ++ld) {
+    const uint32_t l = ell_of(md, uint32_t(ld), b2);
+    const uint32_t hl = pext_dev(l, md.pos_h_ell);
+    __syncthreads();
+    for (int i = threadIdx.x; i < Db * Dg; i += blockDim.x) Ks[i] = Kc[size_t(l) * Db * Dg + i];
+    const double* Xg = X2 + (size_t(ld) * md.drd + rd) * Dg * s;
+    for (int i = threadIdx.x; i < Dg * s; i += blockDim.x) Xs[i] = Xg[i];
+    if (threadIdx.x < f.nHA) {
+      const uint32_t a2 = pdep_dev(uint32_t(threadIdx.x), f.hA_mask);
+      const uint32_t hr = pext_dev(rho_of(md, rd, a2), md.pos_h_rho);
+      wsh[threadIdx.x] = md.Wh[hr * md.Wh_sp + hl * md.Wh_sq];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int idx = threadIdx.x + p * blockDim.x;
+      if (idx < Db * s) {
+        const int b = idx / s, j = idx % s;
+        double t = 0.0;
+        for (int g = 0; g < Dg; ++g) t = fma(Ks[b * Dg + g], Xs[g * s + j], t);
+#pragma unroll
+        for (int h = 0; h < 16; ++h)
+          if (h < f.nHA) acc[h][p] = fma(wsh[h], t, acc[h][p]);
+      }
+    }
+  }
+  double* out = Y2 + size_t(blockIdx.x) * f.nHA * Db * s;
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int idx = threadIdx.x + p * blockDim.x;
+    if (idx < Db * s)
+#pragma unroll
+      for (int h = 0; h < 16; ++h)
+        if (h < f.nHA) out[size_t(h) * Db * s + idx] = acc[h][p];
+  }
+}
+
+// out[(rd, a')] (Da x s) = sum_b' A[a' + da' b'] Y2[rd][b'][hA(a')]
+template <int PT>
+__global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __restrict__ A, int Da, int Db,
+                                                       const double* __restrict__ Y2, int s,
+                                                       double* __restrict__ out) {
+  extern __shared__ double sh[];
+  double* As = sh;             // Da x Db
+  double* Ys = sh + Da * Db;   // Db x s
+  const RowGeom::Med& md = f.md;
+  const uint32_t rd = blockIdx.x / md.da2, a2 = blockIdx.x % md.da2;
+  const uint32_t hA = pext_dev(a2, f.hA_mask);
+  double acc[PT];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) acc[p] = 0.0;
+  for (int b2 = 0; b2 < md.db2; ++b2) {
+    __syncthreads();
+    const double* Ag = A + size_t(a2 + md.da2 * b2) * Da * Db;
+    for (int i = threadIdx.x; i < Da * Db; i += blockDim.x) As[i] = Ag[i];
+    const double* Yg = Y2 + ((size_t(rd) * md.db2 + b2) * f.nHA + hA) * Db * s;
+    for (int i = threadIdx.x; i < Db * s; i += blockDim.x) Ys[i] = Yg[i];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int idx = threadIdx.x + p * blockDim.x;
+      if (idx < Da * s) {
+        const int a = idx / s, j = idx % s;
+        double t = acc[p];
+        for (int b = 0; b < Db; ++b) t = fma(As[a * Db + b], Ys[b * s + j], t);
+        acc[p] = t;
+      }
+    }
+  }
+  double* o = out + size_t(rho_of(md, rd, a2)) * Da * s;
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int idx = threadIdx.x + p * blockDim.x;
+    if (idx < Da * s) o[idx] = acc[p];
+  }
+}
+
+// W2[rd][b'][hL] (Db x s) = sum_a' Wh(h(rd,a'), h'(hL,b')) A[a'+da'b']^T Y[(rd,a')]
+template <int PT>
+__global__ void __launch_bounds__(256) medf_W2_kernel(MedF f, const double* __restrict__ A, int Da, int Db,
+                                                      const double* __restrict__ Y, int s,
+                                                      double* __restrict__ W2) {
+  extern __shared__ double sh[];
+  double* As = sh;             // Da x Db
+  double* Ys = sh + Da * Db;   // Da x s
+  __shared__ double wsh[16];
+  const RowGeom::Med& md = f.md;
+  const uint32_t rd = blockIdx.x / md.db2, b2 = blockIdx.x % md.db2;
+  double acc[16][PT];
+#pragma unroll
+  for (int h = 0; h < 16; ++h)
+#pragma unroll
+    for (int p = 0; p < PT; ++p) acc[h][p] = 0.0;
+  for (int a2 = 0; a2 < md.da2; ++a2) {
+    const uint32_t rho = rho_of(md, rd, uint32_t(a2));
+    const uint32_t hr = pext_dev(rho, md.pos_h_rho);
+    __syncthreads();
+    const double* Ag = A + size_t(a2 + md.da2 * b2) * Da * Db;
+    for (int i = threadIdx.x; i < Da * Db; i += blockDim.x) As[i] = Ag[i];
+    const double* Yg = Y + size_t(rho) * Da * s;
+    for (int i = threadIdx.x; i < Da * s; i += blockDim.x) Ys[i] = Yg[i];
+    if (threadIdx.x < f.nHL) {
+      const uint32_t ld = pdep_dev(uint32_t(threadIdx.x), f.hL_mask);
+      const uint32_t hl = pext_dev(ell_of(md, ld, b2), md.pos_h_ell);
+      wsh[threadIdx.x] = md.Wh[hr * md.Wh_sp + hl * md.Wh_sq];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int idx = threadIdx.x + p * blockDim.x;
+      if (idx < Db * s) {
+        const int b = idx / s, j = idx % s;
+        double t = 0.0;
+        for (int a = 0; a < Da; ++a) t = fma(As[a * Db + b], Ys[a * s + j], t);
+#pragma unroll
+        for (int h = 0; h < 16; ++h)
+          if (h < f.nHL) acc[h][p] = fma(wsh[h], t, acc[h][p]);
+      }
+    }
+  }
+  double* out = W2 + size_t(blockIdx.x) * f.nHL * Db * s;
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int idx = threadIdx.x + p * blockDim.x;
+    if (idx < Db * s)
+#pragma unroll
+      for (int h = 0; h < 16; ++h)
+        if (h < f.nHL) out[size_t(h) * Db * s + idx] = acc[h][p];
+  }
+}
+
+// G2[ld][rd] (Dg x s) = sum_b' K[l(ld,b')]^T W2[rd][b'][hL(ld)]
+template <int PT>
+__global__ void __launch_bounds__(256) medf_G2_kernel(MedF f, const double* __restrict__ Kc, int Db, int Dg,
+                                                      const double* __restrict__ W2, int s,
+                                                      double* __restrict__ G2) {
+  extern __shared__ double sh[];
+  double* Ks = sh;             // Db x Dg
+  double* Ws = sh + Db * Dg;   // Db x s
+  const RowGeom::Med& md = f.md;
+  const uint32_t ld = blockIdx.x / md.drd, rd = blockIdx.x % md.drd;
+  const uint32_t hL = pext_dev(ld, f.hL_mask);
+  double acc[PT];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) acc[p] = 0.0;
+  for (int b2 = 0; b2 < md.db2; ++b2) {
+    const uint32_t l = ell_of(md, ld, uint32_t(b2));
+    __syncthreads();
+    for (int i = threadIdx.x; i < Db * Dg; i += blockDim.x) Ks[i] = Kc[size_t(l) * Db * Dg + i];
+    const double* Wg = W2 + ((size_t(rd) * md.db2 + b2) * f.nHL + hL) * Db * s;
+    for (int i = threadIdx.x; i < Db * s; i += blockDim.x) Ws[i] = Wg[i];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int idx = threadIdx.x + p * blockDim.x;
+      if (idx < Dg * s) {
+        const int g = idx / s, j = idx % s;
+        double t = acc[p];
+        for (int b = 0; b < Db; ++b) t = fma(Ks[b * Dg + g], Ws[b * s + j], t);
+        acc[p] = t;
+      }
+    }
+  }
+  double* o = G2 + size_t(blockIdx.x) * Dg * s;
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int idx = threadIdx.x + p * blockDim.x;
+    if (idx < Dg * s) o[idx] = acc[p];
+  }
+}
+
 // site[sigma][i][g] = V[(sigma*Dg + g)][i]   (V: n_cols x t)
 __global__ void vb_to_site_kernel(const double* __restrict__ V, int ds, int Dg, int t,
                                   double* __restrict__ site) {
@@ -296,6 +508,41 @@ __global__ void fill_kernel(double* __restrict__ x, int64_t n, double v) {
   if (i < n) x[i] = v;
 }
 
+
+static bool make_medf(const RowGeom::Med& md, MedF* f) {
+  const bool partR = (md.pos_d_rho & md.pos_a2) == 0u && (md.pos_d_rho | md.pos_a2) == uint32_t(md.dR - 1);
+  const bool partL = (md.pos_d_ell & md.pos_b2) == 0u && (md.pos_d_ell | md.pos_b2) == uint32_t(md.dL - 1);
+  if (!partR || !partL) return false;
+  f->md = md;
+  f->hA_mask = pext_host(md.pos_h_rho & md.pos_a2, md.pos_a2);
+  f->hL_mask = pext_host(md.pos_h_ell & md.pos_d_ell, md.pos_d_ell);
+  f->nHA = 1 << popcount32(f->hA_mask);
+  f->nHL = 1 << popcount32(f->hL_mask);
+  return f->nHA <= 16 && f->nHL <= 16;
+}
+
+static int pick_pt(int64_t n) {
+  const int opts[] = {1, 2, 4, 6, 8, 12};
+  for (int p : opts)
+    if (int64_t(p) * 256 >= n) return p;
+  return -1;
+}
+
+#define TNB_PT_DISPATCH(PTV, KERNEL, GRID, SHM, ST, ...)                                      \
+  switch (PTV) {                                                                               \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
+    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
+    case 12: hipLaunchKernelGGL(KERNEL<12>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;     \
+    default: fail(TNB_EUNSUPPORTED, "factored mediating tile too large for the register budget"); \
+  }
+
+static void check_lds(size_t bytes) {
+  if (bytes > 65536) fail(TNB_EUNSUPPORTED, "diagram tile exceeds 64 KiB of LDS");
+}
+
 static unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 // -------------------------------------------------------------- the zipper
@@ -304,7 +551,7 @@ struct Zipper {
   const tnb_env_opts& o;
   la::Scratch& ws;
   hipStream_t st;
-  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, SVT;
+  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, SVT, Yf;
 
   // D X for site k of row geometry g; X: (ds*Dg) x s, out: (dm*Da) x s
   void apply(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
@@ -319,6 +566,9 @@ struct Zipper {
       const uint32_t full = c.k ? ((c.k == 32) ? ~0u : ((1u << c.k) - 1u)) : 0u;
       const uint32_t FREE = full & ~c.PL;
       const int nfree = 1 << popcount32(FREE);
+      KTimer _t("site_apply", st, 2.0 * s * Db * double(Dg + Da) * double(c.dL) * nfree,
+                8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
+                       double(c.dL) * Da * s + double(c.dL) * nfree));
       hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
                          k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
                          conn.p, Dg, Xt, s, out);
@@ -333,9 +583,35 @@ struct Zipper {
       la::gemm(md.dld, md.drd, Dg * s, md.db, la::View{md.Wdl, md.Wdl_sq, md.Wdl_sp, 0},
                la::View{X1.p, int64_t(md.dld) * Dg * s, 1, int64_t(Dg) * s}, X2.p,
                int64_t(Dg) * s, int64_t(md.drd) * Dg * s, 1.0, 0.0, ws, st);
-      hipLaunchKernelGGL(med_apply_kernel, dim3(md.dR), dim3(256), size_t(Db) * s * sizeof(double), st,
-                         md, A.data.p, Da, Db, conn.p, Dg, X2.p, s, out);
-      HIPC(hipGetLastError());
+      MedF f;
+      if (make_medf(md, &f)) {
+        ensure(Yf, size_t(md.drd) * md.db2 * f.nHA * Db * s);
+        const int pt1 = pick_pt(int64_t(Db) * s), pt2 = pick_pt(int64_t(Da) * s);
+        check_lds((size_t(Db) * Dg + size_t(Dg) * s) * sizeof(double));
+        check_lds((size_t(Da) * Db + size_t(Db) * s) * sizeof(double));
+        KTimer _t1("medf_Y2", st,
+                   double(md.drd) * md.db2 * md.dld * (2.0 * Db * Dg * s + 2.0 * f.nHA * Db * s),
+                   8.0 * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
+                          double(md.drd) * md.db2 * f.nHA * Db * s));
+        TNB_PT_DISPATCH(pt1, medf_Y2_kernel, dim3(md.drd * md.db2),
+                        (size_t(Db) * Dg + size_t(Dg) * s) * sizeof(double), st, f, conn.p, Db, Dg, X2.p, s, Yf.p);
+        HIPC(hipGetLastError());
+        KTimer _t2("medf_out", st, double(md.drd) * md.da2 * md.db2 * 2.0 * Da * Db * s,
+                   8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHA * Db * s +
+                          double(md.dR) * Da * s));
+        TNB_PT_DISPATCH(pt2, medf_out_kernel, dim3(md.drd * md.da2),
+                        (size_t(Da) * Db + size_t(Db) * s) * sizeof(double), st, f, A.data.p, Da, Db, Yf.p, s, out);
+        HIPC(hipGetLastError());
+      } else {
+        if (double(md.dR) * md.dL > double(1 << 26))
+          fail(TNB_EUNSUPPORTED, "mediating diagram with more than 2^26 (rho, l) pairs");
+        KTimer _t("med_apply", st, double(md.dR) * md.dL * 2.0 * s * Db * double(Dg + Da),
+                  8.0 * (double(md.dL) * Db * Dg + double(md.da2) * md.db2 * Da * Db +
+                         double(md.dld) * md.drd * Dg * s + double(md.dR) * Da * s));
+        hipLaunchKernelGGL(med_apply_kernel, dim3(md.dR), dim3(256), size_t(Db) * s * sizeof(double), st,
+                           md, A.data.p, Da, Db, conn.p, Dg, X2.p, s, out);
+        HIPC(hipGetLastError());
+      }
     }
   }
 
@@ -349,6 +625,9 @@ struct Zipper {
       const uint32_t FREE = full & ~c.Bup;
       const int nfree = 1 << popcount32(FREE);
       double* G = X1.p;  // du x Dg x s
+      KTimer _t("site_applyT", st, 2.0 * s * Db * double(Dg + Da) * double(c.du) * nfree,
+                8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
+                       double(c.dL) * Da * s + double(c.du) * nfree));
       hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
                          k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg,
                          Yin, s, G);
@@ -359,10 +638,36 @@ struct Zipper {
     } else {
       const auto& md = g.med[(k - 1) / 2];
       double* G2 = X2.p;  // [ld][rd][Dg*s]
-      hipLaunchKernelGGL(med_applyT_kernel, dim3(md.dld * md.drd), dim3(256),
-                         size_t(Db) * s * sizeof(double), st, md, A.data.p, Da, Db, conn.p, Dg, Yin,
-                         s, G2);
-      HIPC(hipGetLastError());
+      MedF f;
+      if (make_medf(md, &f)) {
+        ensure(Yf, size_t(md.drd) * md.db2 * f.nHL * Db * s);
+        const int pt1 = pick_pt(int64_t(Db) * s), pt2 = pick_pt(int64_t(Dg) * s);
+        check_lds((size_t(Da) * Db + size_t(Da) * s) * sizeof(double));
+        check_lds((size_t(Db) * Dg + size_t(Db) * s) * sizeof(double));
+        KTimer _t1("medf_W2", st,
+                   double(md.drd) * md.db2 * md.da2 * (2.0 * Da * Db * s + 2.0 * f.nHL * Db * s),
+                   8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
+                          double(md.drd) * md.db2 * f.nHL * Db * s));
+        TNB_PT_DISPATCH(pt1, medf_W2_kernel, dim3(md.drd * md.db2),
+                        (size_t(Da) * Db + size_t(Da) * s) * sizeof(double), st, f, A.data.p, Da, Db, Yin, s, Yf.p);
+        HIPC(hipGetLastError());
+        KTimer _t2("medf_G2", st, double(md.dld) * md.drd * md.db2 * 2.0 * Db * Dg * s,
+                   8.0 * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
+                          double(md.dld) * md.drd * Dg * s));
+        TNB_PT_DISPATCH(pt2, medf_G2_kernel, dim3(md.dld * md.drd),
+                        (size_t(Db) * Dg + size_t(Db) * s) * sizeof(double), st, f, conn.p, Db, Dg, Yf.p, s, G2);
+        HIPC(hipGetLastError());
+      } else {
+        if (double(md.dR) * md.dL > double(1 << 26))
+          fail(TNB_EUNSUPPORTED, "mediating diagram with more than 2^26 (rho, l) pairs");
+        KTimer _t("med_applyT", st, double(md.dR) * md.dL * 2.0 * s * Db * double(Dg + Da),
+                  8.0 * (double(md.dL) * Db * Dg + double(md.da2) * md.db2 * Da * Db +
+                         double(md.dld) * md.drd * Dg * s + double(md.dR) * Da * s));
+        hipLaunchKernelGGL(med_applyT_kernel, dim3(md.dld * md.drd), dim3(256),
+                           size_t(Db) * s * sizeof(double), st, md, A.data.p, Da, Db, conn.p, Dg, Yin,
+                           s, G2);
+        HIPC(hipGetLastError());
+      }
       // H[ld] (db x Dg*s) = Wdl (db x drd) . G2[ld]
       la::gemm(md.dld, md.db, Dg * s, md.drd, la::View{md.Wdl, md.Wdl_sp, md.Wdl_sq, 0},
                la::View{G2, int64_t(Dg) * s, 1, int64_t(md.drd) * Dg * s}, X1.p, int64_t(Dg) * s,
@@ -413,8 +718,6 @@ struct Zipper {
         const auto& md = g.med[(k - 1) / 2];
         x1n = std::max(size_t(md.db) * md.dld * Dg * s, size_t(md.dld) * md.db * Dg * s);
         x2n = size_t(md.dld) * md.drd * Dg * s;
-        if (double(md.dR) * md.dL > double(1 << 26))
-          fail(TNB_EUNSUPPORTED, "mediating diagram with more than 2^26 (rho, l) pairs");
       }
       ensure(X1, x1n);
       ensure(X2, std::max<size_t>(x2n, 1));

@@ -67,6 +67,8 @@ static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double
   const int64_t per = int64_t(M) * N;
   double* P = ws.get(5, size_t(per * batch * nchunk));
   dim3 grid(unsigned(tiles2d), unsigned(batch * nchunk));
+  KTimer _t("gemm", s, 2.0 * M * double(N) * double(K) * batch,
+            8.0 * (double(M) * K + double(K) * N + double(M) * N) * batch);
   hipLaunchKernelGGL(gemm_kernel, grid, dim3(TILE, TILE), 0, s, M, N, K, kchunk, A.p, A.rs, A.cs,
                      A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
   HIPC(hipGetLastError());
@@ -199,6 +201,7 @@ void eigh(double* G, int s, double* V, double* lam, hipStream_t st) {
   if (s <= 0) return;
   if (s > 1000) fail(TNB_EUNSUPPORTED, "eigensolver limited to 1000 x 1000");
   size_t shm = 2560 * sizeof(double);
+  KTimer _t("eigh", st, 0.0, 16.0 * s * s);
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), shm, st, G, s, V, lam);
   HIPC(hipGetLastError());
 }
