@@ -181,6 +181,7 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
                 pd_log = max(pd_log, sc[win[M]])
             rec = dict(n=n, candidates=len(bb), groups=len(win), kept=len(keep))
             if trace:
+                rec["p"] = np.where(alive[:, None], qpos / np.where(alive, Zb, 1.0)[:, None], 0.0)
                 rec["X"] = X[bb[keep]].copy()
                 rec["X"][:, n] = xx[keep]
                 rec["logp"] = sc[keep].copy()

@@ -16,6 +16,8 @@
 // across parents, boundaries are equal iff the parents' boundary words are
 // equal (class id) and the reduced x agree.  Ordering uses a bitonic sort of
 // (boundary key, -score, parent, x): deterministic, no atomics.
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 
 #include "env.h"
@@ -327,7 +329,8 @@ __global__ void group_kernel(const double* __restrict__ score, int k, uint32_t U
     }
   } else if (idx < nb * d) {
     const double s = score[idx];
-    if (s > -INFINITY) cnd = Cand{0ull, score_key(s), uint32_t(idx / d), uint32_t(idx % d)};
+    // no merge (last cluster): every candidate is its own group
+    if (s > -INFINITY) cnd = Cand{uint64_t(idx), score_key(s), uint32_t(idx / d), uint32_t(idx % d)};
   }
   out[idx] = cnd;
 }
@@ -710,6 +713,18 @@ extern "C" tnb_status tnb_branch_step(tnb_beam* bm, double* p_disc_log, tnb_stre
     HIPC(hipStreamSynchronize(st));
     int64_t wp2 = 1;
     while (wp2 < nw) wp2 <<= 1;
+    if (std::getenv("TNB_DEBUG")) {
+      std::vector<uint32_t> hc(nb);
+      if (!last) HIPC(hipMemcpy(hc.data(), bm->cls.p, nb * sizeof(uint32_t), hipMemcpyDeviceToHost));
+      std::vector<Cand> hcand(std::min<int64_t>(np2, 64));
+      HIPC(hipMemcpy(hcand.data(), bm->cand.p, hcand.size() * sizeof(Cand), hipMemcpyDeviceToHost));
+      std::fprintf(stderr, "[tnb] step %d nb %d Un %x ncand %lld np2 %lld nw %lld W %d cls:", n, nb, Un,
+                   (long long)ncand, (long long)np2, (long long)nw, W);
+      for (auto v : hc) std::fprintf(stderr, " %u", v);
+      std::fprintf(stderr, "\n  sorted gkeys:");
+      for (auto& c : hcand) std::fprintf(stderr, " %llx/%u/%u", (unsigned long long)c.gkey, c.b, c.x);
+      std::fprintf(stderr, "\n");
+    }
     hipLaunchKernelGGL(fill_cand_kernel, dim3(nblk(wp2)), dim3(256), 0, st, bm->win.p, int64_t(0), wp2);
     hipLaunchKernelGGL(compact_kernel, dim3(nblk(np2)), dim3(256), 0, st, bm->cand.p, bm->flag.p, bm->pos.p, np2,
                        bm->win.p);
