@@ -98,7 +98,8 @@ typedef struct {
   int32_t chi;           /* bond dimension of the boundary MPSs, >= 1        */
   int32_t sketch_extra;  /* oversampling: sketch width is 2*chi + extra      */
   int32_t power_iters;   /* subspace iterations of the randomized SVD        */
-  double cut;            /* singular values below cut*sigma_max are dropped  */
+  double cut;            /* singular values below cut*sigma_max are dropped;
+                            1e-7 <= cut < 1                                  */
   uint64_t seed;         /* Rademacher sketch seed (SplitMix64, counter-based)*/
 } tnb_env_opts;
 

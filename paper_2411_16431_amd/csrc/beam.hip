@@ -531,25 +531,33 @@ static void row_envs(tnb_beam* bm, int r, hipStream_t st) {
     const Site& A2m = psi.sites[2 * c - 1];
     const int64_t d = int64_t(1) << cc.k;
     ensure(bm->u, size_t(nb) * d * A2c.dl);
+    {
     KTimer _tu("renv_u", st, 2.0 * nb * double(d) * A2c.dl * A2c.dr, 8.0 * (double(nb) * d * A2c.dl + A2c.size()));
     hipLaunchKernelGGL(renv_u_kernel, dim3(nblk(int64_t(nb) * d * A2c.dl)), dim3(256), 0, st, cc, A2c.data.p,
                        A2c.dl, A2c.dr, bm->R[c].p, nb, bm->u.p);
+    }
     ensure(bm->U, size_t(nb) * cc.dxh * cc.dbd * A2c.dl);
+    {
     KTimer _tU("renv_U", st, 2.0 * nb * double(d) * A2c.dl, 8.0 * (double(nb) * d * A2c.dl));
     hipLaunchKernelGGL(renv_U_kernel, dim3(nblk(int64_t(nb) * cc.dxh * cc.dbd * A2c.dl)), dim3(256), 0, st, cc,
                        bm->X.p, bm->ncell, bm->u.p, nb, A2c.dl, bm->U.p);
+    }
     ensure(bm->V, size_t(nb) * cc.da2 * cc.dxh * A2m.dl);
+    {
     KTimer _tV("renv_V", st, 2.0 * nb * double(cc.da2) * cc.dxh * A2m.dl * cc.dbd * A2m.dr,
                8.0 * (A2m.size() + double(nb) * cc.dxh * cc.dbd * A2c.dl + double(nb) * cc.da2 * cc.dxh * A2m.dl));
     hipLaunchKernelGGL(renv_V_kernel, dim3(nblk(int64_t(nb) * cc.da2 * cc.dxh * A2m.dl)), dim3(256), 0, st, cc,
                        A2m.data.p, A2m.dl, A2m.dr, bm->U.p, nb, bm->V.p);
+    }
     const int dpi_prev = bm->geo[c - 1].dpi;
     DevBuf<double>& Rn = bm->R[c - 1];
     Rn.alloc(size_t(nb) * A2m.dl * dpi_prev);
+    {
     KTimer _tR("renv_R", st, 2.0 * nb * double(A2m.dl) * dpi_prev * cc.dxh,
                8.0 * (double(nb) * cc.da2 * cc.dxh * A2m.dl + double(nb) * A2m.dl * dpi_prev));
     hipLaunchKernelGGL(renv_R_kernel, dim3(nblk(int64_t(nb) * A2m.dl * dpi_prev)), dim3(256), 0, st, cc, dpi_prev,
                        bm->V.p, nb, A2m.dl, Rn.p);
+    }
     hipLaunchKernelGGL(normalise_rows_kernel, dim3(nb), dim3(256), 0, st, Rn.p, int64_t(A2m.dl) * dpi_prev, nb);
     HIPC(hipGetLastError());
   }
@@ -583,10 +591,12 @@ static void compute_q(tnb_beam* bm, hipStream_t st) {
                        bm->X.p, bm->ncell, bm->L.p, bm->Ld, A2m.data.p, A2m.dl, A2m.dr, nb, bm->T.p);
   }
   ensure(bm->q, size_t(nb) * d);
+  {
   KTimer _tq("beam_q", st, double(nb) * d * (2.0 * A2c.dl * A2c.dr + 2.0 * A2c.dr),
              8.0 * (double(nb) * d + A2c.size() + double(bm->nanc) * A2c.dr * cc.dpi + double(nb) * cc.dbd * A2c.dl));
   hipLaunchKernelGGL(beam_q_kernel, dim3(nblk(int64_t(nb) * d)), dim3(256), 0, st, cc, c > 0 ? 1 : 0, left < 0 ? 0 : left,
                      bm->X.p, bm->ncell, bm->T.p, A2c.data.p, A2c.dl, A2c.dr, bm->R[c].p, bm->rid.p, nb, bm->q.p);
+  }
   HIPC(hipGetLastError());
 }
 

@@ -26,7 +26,9 @@ inline void hip_check(hipError_t e, const char* what) {
     fail(TNB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   }
 }
-#define HIPC(x) ::tnb::hip_check((x), #x)
+#define TNB_STR2(x) #x
+#define TNB_STR(x) TNB_STR2(x)
+#define HIPC(x) ::tnb::hip_check((x), #x " [" __FILE__ ":" TNB_STR(__LINE__) "]")
 
 void set_error(const std::string& msg);
 void clear_error();

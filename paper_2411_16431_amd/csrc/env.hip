@@ -9,6 +9,7 @@
 //   site^T    G[u][g][j]    = sum_{x: P^up x = u} w(x) K[rho(x)]^T A[v'(x)]^T Y[l(x)]
 //   mediating out[rho][a][j] = sum_l Wh(rho,l) A[a'(rho)+da' b'(l)] K[l] X2[l_d(l)][rho_d(rho)]
 //   mediating^T G2[l_d][rho_d] = sum_{rho in rho_d, l in l_d} Wh K[l]^T A[..]^T Y[rho]
+// The mediating sums are evaluated in the factored order described below.
 // Each output block is owned by one workgroup (no atomics: deterministic).
 #include <memory>
 
@@ -174,102 +175,25 @@ __global__ void site_applyT_kernel(int k, uint32_t Bup, uint32_t FREE, int nfree
   }
 }
 
-// out[rho] (Da x s) for rho = blockIdx.x; X2: [l_d][rho_d][Dg][s].
-__global__ void med_apply_kernel(RowGeom::Med md, const double* __restrict__ A, int Da, int Db,
-                                 const double* __restrict__ Kc, int Dg,
-                                 const double* __restrict__ X2, int s, double* __restrict__ out) {
-  extern __shared__ double T[];  // Db x s
-  const uint32_t rho = blockIdx.x;
-  double* o = out + size_t(rho) * Da * s;
-  for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) o[idx] = 0.0;
-  const uint32_t rd = pext_dev(rho, md.pos_d_rho), a2 = pext_dev(rho, md.pos_a2);
-  const uint32_t hr = pext_dev(rho, md.pos_h_rho);
-  for (int l = 0; l < md.dL; ++l) {
-    const uint32_t ld = pext_dev(uint32_t(l), md.pos_d_ell), b2 = pext_dev(uint32_t(l), md.pos_b2);
-    const double wh = md.Wh[hr * md.Wh_sp + pext_dev(uint32_t(l), md.pos_h_ell) * md.Wh_sq];
-    const double* Kr = Kc + size_t(l) * Db * Dg;
-    const double* Xs = X2 + (size_t(ld) * md.drd + rd) * Dg * s;
-    const double* Av = A + size_t(a2 + md.da2 * b2) * Da * Db;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
-      const int b = idx / s, j = idx % s;
-      double acc = 0.0;
-      for (int g = 0; g < Dg; ++g) acc = fma(Kr[b * Dg + g], Xs[g * s + j], acc);
-      T[idx] = acc;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) {
-      const int a = idx / s, j = idx % s;
-      double acc = 0.0;
-      for (int b = 0; b < Db; ++b) acc = fma(Av[a * Db + b], T[b * s + j], acc);
-      o[idx] = fma(wh, acc, o[idx]);
-    }
-  }
-}
-
-// G2[l_d][rho_d] (Dg x s), block = (l_d, rho_d).
-__global__ void med_applyT_kernel(RowGeom::Med md, const double* __restrict__ A, int Da, int Db,
-                                  const double* __restrict__ Kc, int Dg,
-                                  const double* __restrict__ Y, int s, double* __restrict__ G2) {
-  extern __shared__ double T[];  // Db x s
-  const uint32_t ld = blockIdx.x / md.drd, rd = blockIdx.x % md.drd;
-  double* o = G2 + size_t(blockIdx.x) * Dg * s;
-  for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) o[idx] = 0.0;
-  const uint32_t freeR = uint32_t(md.dR - 1) & ~md.pos_d_rho;
-  const uint32_t freeL = uint32_t(md.dL - 1) & ~md.pos_d_ell;
-  const int nR = md.dR / md.drd, nL = md.dL / md.dld;
-  for (int fr = 0; fr < nR; ++fr) {
-    const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(uint32_t(fr), freeR);
-    const uint32_t a2 = pext_dev(rho, md.pos_a2), hr = pext_dev(rho, md.pos_h_rho);
-    const double* Yr = Y + size_t(rho) * Da * s;
-    for (int fl = 0; fl < nL; ++fl) {
-      const uint32_t l = pdep_dev(ld, md.pos_d_ell) | pdep_dev(uint32_t(fl), freeL);
-      const uint32_t b2 = pext_dev(l, md.pos_b2);
-      const double wh = md.Wh[hr * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
-      const double* Kr = Kc + size_t(l) * Db * Dg;
-      const double* Av = A + size_t(a2 + md.da2 * b2) * Da * Db;
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
-        const int b = idx / s, j = idx % s;
-        double acc = 0.0;
-        for (int a = 0; a < Da; ++a) acc = fma(Av[a * Db + b], Yr[a * s + j], acc);
-        T[idx] = acc;
-      }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) {
-        const int g = idx / s, j = idx % s;
-        double acc = 0.0;
-        for (int b = 0; b < Db; ++b) acc = fma(Kr[b * Dg + g], T[b * s + j], acc);
-        o[idx] = fma(wh, acc, o[idx]);
-      }
-    }
-  }
-}
-
 // ---- factored mediating diagram --------------------------------------------
-// Used when the spins of (r,c) facing column c+1 split into those facing the
-// upper diagonal cell (rho_d) and those facing the lower one (a'), with no
-// overlap, and likewise for l = (l_d, b').  Then the horizontal weight
-// depends on rho only through rho_d and the a'-bits hA of its horizontal
-// spins, and on l through l_d and b', and the (rho, l) double sum factors:
-//   apply :  Y2[rd][b'][hA] = sum_ld Wh(h(rd,hA), h'(ld,b')) K[l(ld,b')] X2[ld][rd]
-//            out[(rd,a')]   = sum_b' A[a' + da' b'] Y2[rd][b'][hA(a')]
-//   applyT:  W2[rd][b'][hL] = sum_a' Wh(h(rd,a'), h'(hL,b')) A[a'+da'b']^T Y[(rd,a')]
-//            G2[ld][rd]     = sum_b' K[l(ld,b')]^T W2[rd][b'][hL(ld)]
+// W_dl sees rho only through rho_d (spins facing the upper-right cell), W_dr
+// sees l only through l_d, and the horizontal weight sees rho through its
+// horizontal bits h = (bits in rho_d, bits outside rho_d = hR) and l through
+// h' = (bits in b', bits outside b' = hL).  The (rho, l) double sum is split
+// at b' (the lower-left diagonal bits of l):
+//   apply :  Y2[rd][b'][hR]   = sum_{l: b'(l)=b'} Wh(h(rd,hR), h'(l)) K[l] X2[l_d(l)][rd]
+//            out[rho]         = sum_b' A[a'(rho) + da' b'] Y2[rd(rho)][b'][hR(rho)]
+//   applyT:  W2[rd][b'][hL]   = sum_{rho: rd(rho)=rd} Wh(h(rho), h'(b',hL)) A[a'(rho)+da'b']^T Y[rho]
+//            G2[ld][rd]       = sum_{l: l_d(l)=ld} K[l]^T W2[rd][b'(l)][hL(l)]
+// Bins (hR or hL values) are spread over the grid in chunks of 16 held in
+// registers.  Every output block is owned by one workgroup: no atomics.
 struct MedF {
   RowGeom::Med md;
-  int hA_bits = 0;           // a'-space mask of the horizontal spins
-  uint32_t hA_mask = 0;
-  uint32_t hL_mask = 0;      // l_d-space mask of the horizontal spins of l
-  int nHA = 1, nHL = 1;
+  uint32_t hR_pos = 0;   // horizontal bits of rho outside rho_d (positions within rho)
+  uint32_t hL_pos = 0;   // horizontal bits of l outside b' (positions within l)
+  int nHR = 1, nHL = 1;
+  int chR = 1, chL = 1;  // chunks of 16 bins
 };
-
-__device__ __forceinline__ uint32_t rho_of(const RowGeom::Med& md, uint32_t rd, uint32_t a2) {
-  return pdep_dev(rd, md.pos_d_rho) | pdep_dev(a2, md.pos_a2);
-}
-__device__ __forceinline__ uint32_t ell_of(const RowGeom::Med& md, uint32_t ld, uint32_t b2) {
-  return pdep_dev(ld, md.pos_d_ell) | pdep_dev(b2, md.pos_b2);
-}
 
 template <int PT>
 __global__ void __launch_bounds__(256) medf_Y2_kernel(MedF f, const double* __restrict__ Kc, int Db, int Dg,
@@ -278,26 +202,31 @@ __global__ void __launch_bounds__(256) medf_Y2_kernel(MedF f, const double* __re
   extern __shared__ double sh[];
   double* Ks = sh;              // Db x Dg
   double* Xs = sh + Db * Dg;    // Dg x s
-  __shared__ double wsh[16];
+  double* wsh = Xs + Dg * s;    // 16 horizontal weights
   const RowGeom::Med& md = f.md;
-  const uint32_t rd = blockIdx.x / md.db2, b2 = blockIdx.x % md.db2;
+  const uint32_t chunk = blockIdx.x % f.chR;
+  const uint32_t pair = blockIdx.x / f.chR;
+  const uint32_t rd = pair / md.db2, b2 = pair % md.db2;
+  const uint32_t rho_d_bits = pdep_dev(rd, md.pos_d_rho);
+  const int nb = min(16, f.nHR - int(chunk) * 16);
   double acc[16][PT];
 #pragma unroll
   for (int h = 0; h < 16; ++h)
 #pragma unroll
     for (int p = 0; p < PT; ++p) acc[h][p] = 0.0;
-  const int nld = md.dld;
-  for (int ld = 0; ld < nld; ++ld) {
-    const uint32_t l = ell_of(md, uint32_t(ld), b2);
+  const uint32_t freeL = uint32_t(md.dL - 1) & ~md.pos_b2;
+  const int nl = md.dL / md.db2;
+  for (int fl = 0; fl < nl; ++fl) {
+    const uint32_t l = pdep_dev(b2, md.pos_b2) | pdep_dev(uint32_t(fl), freeL);
+    const uint32_t ld = pext_dev(l, md.pos_d_ell);
     const uint32_t hl = pext_dev(l, md.pos_h_ell);
     __syncthreads();
     for (int i = threadIdx.x; i < Db * Dg; i += blockDim.x) Ks[i] = Kc[size_t(l) * Db * Dg + i];
     const double* Xg = X2 + (size_t(ld) * md.drd + rd) * Dg * s;
     for (int i = threadIdx.x; i < Dg * s; i += blockDim.x) Xs[i] = Xg[i];
-    if (threadIdx.x < f.nHA) {
-      const uint32_t a2 = pdep_dev(uint32_t(threadIdx.x), f.hA_mask);
-      const uint32_t hr = pext_dev(rho_of(md, rd, a2), md.pos_h_rho);
-      wsh[threadIdx.x] = md.Wh[hr * md.Wh_sp + hl * md.Wh_sq];
+    if (int(threadIdx.x) < nb) {
+      const uint32_t rho = rho_d_bits | pdep_dev(chunk * 16u + threadIdx.x, f.hR_pos);
+      wsh[threadIdx.x] = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + hl * md.Wh_sq];
     }
     __syncthreads();
 #pragma unroll
@@ -309,22 +238,22 @@ __global__ void __launch_bounds__(256) medf_Y2_kernel(MedF f, const double* __re
         for (int g = 0; g < Dg; ++g) t = fma(Ks[b * Dg + g], Xs[g * s + j], t);
 #pragma unroll
         for (int h = 0; h < 16; ++h)
-          if (h < f.nHA) acc[h][p] = fma(wsh[h], t, acc[h][p]);
+          if (h < nb) acc[h][p] = fma(wsh[h], t, acc[h][p]);
       }
     }
   }
-  double* out = Y2 + size_t(blockIdx.x) * f.nHA * Db * s;
+  double* out = Y2 + (size_t(pair) * f.nHR + chunk * 16u) * Db * s;
 #pragma unroll
   for (int p = 0; p < PT; ++p) {
     const int idx = threadIdx.x + p * blockDim.x;
     if (idx < Db * s)
 #pragma unroll
       for (int h = 0; h < 16; ++h)
-        if (h < f.nHA) out[size_t(h) * Db * s + idx] = acc[h][p];
+        if (h < nb) out[size_t(h) * Db * s + idx] = acc[h][p];
   }
 }
 
-// out[(rd, a')] (Da x s) = sum_b' A[a' + da' b'] Y2[rd][b'][hA(a')]
+// out[rho] (Da x s) = sum_b' A[a'(rho) + da' b'] Y2[rd(rho)][b'][hR(rho)]
 template <int PT>
 __global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __restrict__ A, int Da, int Db,
                                                        const double* __restrict__ Y2, int s,
@@ -333,8 +262,9 @@ __global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __r
   double* As = sh;             // Da x Db
   double* Ys = sh + Da * Db;   // Db x s
   const RowGeom::Med& md = f.md;
-  const uint32_t rd = blockIdx.x / md.da2, a2 = blockIdx.x % md.da2;
-  const uint32_t hA = pext_dev(a2, f.hA_mask);
+  const uint32_t rho = blockIdx.x;
+  const uint32_t rd = pext_dev(rho, md.pos_d_rho), a2 = pext_dev(rho, md.pos_a2);
+  const uint32_t hR = pext_dev(rho, f.hR_pos);
   double acc[PT];
 #pragma unroll
   for (int p = 0; p < PT; ++p) acc[p] = 0.0;
@@ -342,7 +272,7 @@ __global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __r
     __syncthreads();
     const double* Ag = A + size_t(a2 + md.da2 * b2) * Da * Db;
     for (int i = threadIdx.x; i < Da * Db; i += blockDim.x) As[i] = Ag[i];
-    const double* Yg = Y2 + ((size_t(rd) * md.db2 + b2) * f.nHA + hA) * Db * s;
+    const double* Yg = Y2 + ((size_t(rd) * md.db2 + b2) * f.nHR + hR) * Db * s;
     for (int i = threadIdx.x; i < Db * s; i += blockDim.x) Ys[i] = Yg[i];
     __syncthreads();
 #pragma unroll
@@ -356,7 +286,7 @@ __global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __r
       }
     }
   }
-  double* o = out + size_t(rho_of(md, rd, a2)) * Da * s;
+  double* o = out + size_t(rho) * Da * s;
 #pragma unroll
   for (int p = 0; p < PT; ++p) {
     const int idx = threadIdx.x + p * blockDim.x;
@@ -364,7 +294,7 @@ __global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __r
   }
 }
 
-// W2[rd][b'][hL] (Db x s) = sum_a' Wh(h(rd,a'), h'(hL,b')) A[a'+da'b']^T Y[(rd,a')]
+// W2[rd][b'][hL] (Db x s) = sum_{rho in rd} Wh(h(rho), h'(b',hL)) A[a'(rho)+da'b']^T Y[rho]
 template <int PT>
 __global__ void __launch_bounds__(256) medf_W2_kernel(MedF f, const double* __restrict__ A, int Da, int Db,
                                                       const double* __restrict__ Y, int s,
@@ -372,26 +302,32 @@ __global__ void __launch_bounds__(256) medf_W2_kernel(MedF f, const double* __re
   extern __shared__ double sh[];
   double* As = sh;             // Da x Db
   double* Ys = sh + Da * Db;   // Da x s
-  __shared__ double wsh[16];
+  double* wsh = Ys + Da * s;   // 16 horizontal weights
   const RowGeom::Med& md = f.md;
-  const uint32_t rd = blockIdx.x / md.db2, b2 = blockIdx.x % md.db2;
+  const uint32_t chunk = blockIdx.x % f.chL;
+  const uint32_t pair = blockIdx.x / f.chL;
+  const uint32_t rd = pair / md.db2, b2 = pair % md.db2;
+  const uint32_t b2_bits = pdep_dev(b2, md.pos_b2);
+  const int nb = min(16, f.nHL - int(chunk) * 16);
   double acc[16][PT];
 #pragma unroll
   for (int h = 0; h < 16; ++h)
 #pragma unroll
     for (int p = 0; p < PT; ++p) acc[h][p] = 0.0;
-  for (int a2 = 0; a2 < md.da2; ++a2) {
-    const uint32_t rho = rho_of(md, rd, uint32_t(a2));
+  const uint32_t freeR = uint32_t(md.dR - 1) & ~md.pos_d_rho;
+  const int nr = md.dR / md.drd;
+  for (int fr = 0; fr < nr; ++fr) {
+    const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(uint32_t(fr), freeR);
+    const uint32_t a2 = pext_dev(rho, md.pos_a2);
     const uint32_t hr = pext_dev(rho, md.pos_h_rho);
     __syncthreads();
     const double* Ag = A + size_t(a2 + md.da2 * b2) * Da * Db;
     for (int i = threadIdx.x; i < Da * Db; i += blockDim.x) As[i] = Ag[i];
     const double* Yg = Y + size_t(rho) * Da * s;
     for (int i = threadIdx.x; i < Da * s; i += blockDim.x) Ys[i] = Yg[i];
-    if (threadIdx.x < f.nHL) {
-      const uint32_t ld = pdep_dev(uint32_t(threadIdx.x), f.hL_mask);
-      const uint32_t hl = pext_dev(ell_of(md, ld, b2), md.pos_h_ell);
-      wsh[threadIdx.x] = md.Wh[hr * md.Wh_sp + hl * md.Wh_sq];
+    if (int(threadIdx.x) < nb) {
+      const uint32_t l = b2_bits | pdep_dev(chunk * 16u + threadIdx.x, f.hL_pos);
+      wsh[threadIdx.x] = md.Wh[hr * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
     }
     __syncthreads();
 #pragma unroll
@@ -403,22 +339,22 @@ __global__ void __launch_bounds__(256) medf_W2_kernel(MedF f, const double* __re
         for (int a = 0; a < Da; ++a) t = fma(As[a * Db + b], Ys[a * s + j], t);
 #pragma unroll
         for (int h = 0; h < 16; ++h)
-          if (h < f.nHL) acc[h][p] = fma(wsh[h], t, acc[h][p]);
+          if (h < nb) acc[h][p] = fma(wsh[h], t, acc[h][p]);
       }
     }
   }
-  double* out = W2 + size_t(blockIdx.x) * f.nHL * Db * s;
+  double* out = W2 + (size_t(pair) * f.nHL + chunk * 16u) * Db * s;
 #pragma unroll
   for (int p = 0; p < PT; ++p) {
     const int idx = threadIdx.x + p * blockDim.x;
     if (idx < Db * s)
 #pragma unroll
       for (int h = 0; h < 16; ++h)
-        if (h < f.nHL) out[size_t(h) * Db * s + idx] = acc[h][p];
+        if (h < nb) out[size_t(h) * Db * s + idx] = acc[h][p];
   }
 }
 
-// G2[ld][rd] (Dg x s) = sum_b' K[l(ld,b')]^T W2[rd][b'][hL(ld)]
+// G2[ld][rd] (Dg x s) = sum_{l in ld} K[l]^T W2[rd][b'(l)][hL(l)]
 template <int PT>
 __global__ void __launch_bounds__(256) medf_G2_kernel(MedF f, const double* __restrict__ Kc, int Db, int Dg,
                                                       const double* __restrict__ W2, int s,
@@ -428,12 +364,14 @@ __global__ void __launch_bounds__(256) medf_G2_kernel(MedF f, const double* __re
   double* Ws = sh + Db * Dg;   // Db x s
   const RowGeom::Med& md = f.md;
   const uint32_t ld = blockIdx.x / md.drd, rd = blockIdx.x % md.drd;
-  const uint32_t hL = pext_dev(ld, f.hL_mask);
   double acc[PT];
 #pragma unroll
   for (int p = 0; p < PT; ++p) acc[p] = 0.0;
-  for (int b2 = 0; b2 < md.db2; ++b2) {
-    const uint32_t l = ell_of(md, ld, uint32_t(b2));
+  const uint32_t freeL = uint32_t(md.dL - 1) & ~md.pos_d_ell;
+  const int nl = md.dL / md.dld;
+  for (int fl = 0; fl < nl; ++fl) {
+    const uint32_t l = pdep_dev(ld, md.pos_d_ell) | pdep_dev(uint32_t(fl), freeL);
+    const uint32_t b2 = pext_dev(l, md.pos_b2), hL = pext_dev(l, f.hL_pos);
     __syncthreads();
     for (int i = threadIdx.x; i < Db * Dg; i += blockDim.x) Ks[i] = Kc[size_t(l) * Db * Dg + i];
     const double* Wg = W2 + ((size_t(rd) * md.db2 + b2) * f.nHL + hL) * Db * s;
@@ -509,16 +447,14 @@ __global__ void fill_kernel(double* __restrict__ x, int64_t n, double v) {
 }
 
 
-static bool make_medf(const RowGeom::Med& md, MedF* f) {
-  const bool partR = (md.pos_d_rho & md.pos_a2) == 0u && (md.pos_d_rho | md.pos_a2) == uint32_t(md.dR - 1);
-  const bool partL = (md.pos_d_ell & md.pos_b2) == 0u && (md.pos_d_ell | md.pos_b2) == uint32_t(md.dL - 1);
-  if (!partR || !partL) return false;
+static void make_medf(const RowGeom::Med& md, MedF* f) {
   f->md = md;
-  f->hA_mask = pext_host(md.pos_h_rho & md.pos_a2, md.pos_a2);
-  f->hL_mask = pext_host(md.pos_h_ell & md.pos_d_ell, md.pos_d_ell);
-  f->nHA = 1 << popcount32(f->hA_mask);
-  f->nHL = 1 << popcount32(f->hL_mask);
-  return f->nHA <= 16 && f->nHL <= 16;
+  f->hR_pos = md.pos_h_rho & ~md.pos_d_rho;
+  f->hL_pos = md.pos_h_ell & ~md.pos_b2;
+  f->nHR = 1 << popcount32(f->hR_pos);
+  f->nHL = 1 << popcount32(f->hL_pos);
+  f->chR = (f->nHR + 15) / 16;
+  f->chL = (f->nHL + 15) / 16;
 }
 
 static int pick_pt(int64_t n) {
@@ -528,19 +464,42 @@ static int pick_pt(int64_t n) {
   return -1;
 }
 
+#define TNB_PT_CASE(P, KERNEL, GRID, SHM, ST, ...) \
+    case P: allow_big_lds(KERNEL<P>, SHM); hipLaunchKernelGGL(KERNEL<P>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;
 #define TNB_PT_DISPATCH(PTV, KERNEL, GRID, SHM, ST, ...)                                      \
   switch (PTV) {                                                                               \
-    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
-    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
-    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
-    case 6: hipLaunchKernelGGL(KERNEL<6>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
-    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;       \
-    case 12: hipLaunchKernelGGL(KERNEL<12>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;     \
+    TNB_PT_CASE(1, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
+    TNB_PT_CASE(2, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
+    TNB_PT_CASE(4, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
+    TNB_PT_CASE(6, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
+    TNB_PT_CASE(8, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
+    TNB_PT_CASE(12, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                        \
     default: fail(TNB_EUNSUPPORTED, "factored mediating tile too large for the register budget"); \
   }
 
+constexpr size_t kMaxLds = 163840;  // gfx950: 160 KiB of LDS per workgroup
+
 static void check_lds(size_t bytes) {
-  if (bytes > 65536) fail(TNB_EUNSUPPORTED, "diagram tile exceeds 64 KiB of LDS");
+  if (bytes > kMaxLds) fail(TNB_EUNSUPPORTED, "diagram tile exceeds the 160 KiB of LDS");
+}
+
+// Raise a kernel's dynamic-LDS limit when a launch needs more than 64 KiB.
+template <class K>
+static void allow_big_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    HIPC(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+}
+
+// Copy `width` columns starting at c0 of a row-major (n x lds) matrix into
+// columns d0.. of a row-major (n x ldd) matrix.
+__global__ void copy_cols_kernel(const double* __restrict__ src, int64_t n, int lds, int c0, int width,
+                                 double* __restrict__ dst, int ldd, int d0) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * width) return;
+  const int64_t i = idx / width;
+  const int j = int(idx % width);
+  dst[i * ldd + d0 + j] = src[i * lds + c0 + j];
 }
 
 static unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
@@ -551,11 +510,46 @@ struct Zipper {
   const tnb_env_opts& o;
   la::Scratch& ws;
   hipStream_t st;
-  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, SVT, Yf;
+  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, SVT, Yf, Cin, Cout;
+
+  // Widest sketch block whose diagram tiles fit the LDS and register budget.
+  static int block_width(int Da, int Db, int Dg, int s) {
+    const int mx = std::max(Da, std::max(Db, Dg));
+    int w = s;
+    while (w > 1 && (int64_t(mx) * w > 12 * 256 ||
+                     (size_t(mx) * mx + size_t(mx) * w + 16) * sizeof(double) > kMaxLds))
+      --w;
+    return w;
+  }
+
+  // D X (or D^T X) over sketch blocks: every column is independent, so wide
+  // sketches are processed in blocks that fit on chip.
+  template <bool T>
+  void apply_cols(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
+                  double* out, int64_t n_in, int64_t n_out) {
+    const int w = block_width(A.dl, A.dr, Dg, s);
+    if (w >= s) {
+      if (T) applyT_block(g, k, A, Dg, dm, X, s, out);
+      else apply_block(g, k, A, Dg, dm, X, s, out);
+      return;
+    }
+    ensure(Cin, size_t(n_in) * w);
+    ensure(Cout, size_t(n_out) * w);
+    for (int c0 = 0; c0 < s; c0 += w) {
+      const int wc = std::min(w, s - c0);
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(n_in * wc)), dim3(256), 0, st, X, n_in, s, c0, wc,
+                         Cin.p, wc, 0);
+      if (T) applyT_block(g, k, A, Dg, dm, Cin.p, wc, Cout.p);
+      else apply_block(g, k, A, Dg, dm, Cin.p, wc, Cout.p);
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(n_out * wc)), dim3(256), 0, st, Cout.p, n_out, wc, 0, wc,
+                         out, s, c0);
+      HIPC(hipGetLastError());
+    }
+  }
 
   // D X for site k of row geometry g; X: (ds*Dg) x s, out: (dm*Da) x s
-  void apply(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
-             double* out) {
+  void apply_block(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
+                   double* out) {
     const int Da = A.dl, Db = A.dr;
     if (k % 2 == 0) {
       const auto& c = g.col[k / 2];
@@ -566,13 +560,16 @@ struct Zipper {
       const uint32_t full = c.k ? ((c.k == 32) ? ~0u : ((1u << c.k) - 1u)) : 0u;
       const uint32_t FREE = full & ~c.PL;
       const int nfree = 1 << popcount32(FREE);
+{
       KTimer _t("site_apply", st, 2.0 * s * Db * double(Dg + Da) * double(c.dL) * nfree,
                 8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
                        double(c.dL) * Da * s + double(c.dL) * nfree));
+      allow_big_lds(site_apply_kernel, size_t(Db) * s * sizeof(double));
       hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
                          k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
                          conn.p, Dg, Xt, s, out);
       HIPC(hipGetLastError());
+        }
     } else {
       const auto& md = g.med[(k - 1) / 2];
       // X1[b] (dld x Dg*s) = Wdr^T . X[b]  with X[(b*da + a)][Dg*s]
@@ -584,40 +581,36 @@ struct Zipper {
                la::View{X1.p, int64_t(md.dld) * Dg * s, 1, int64_t(Dg) * s}, X2.p,
                int64_t(Dg) * s, int64_t(md.drd) * Dg * s, 1.0, 0.0, ws, st);
       MedF f;
-      if (make_medf(md, &f)) {
-        ensure(Yf, size_t(md.drd) * md.db2 * f.nHA * Db * s);
+      make_medf(md, &f);
+      {
+        ensure(Yf, size_t(md.drd) * md.db2 * f.nHR * Db * s);
         const int pt1 = pick_pt(int64_t(Db) * s), pt2 = pick_pt(int64_t(Da) * s);
-        check_lds((size_t(Db) * Dg + size_t(Dg) * s) * sizeof(double));
+        check_lds((size_t(Db) * Dg + size_t(Dg) * s + 16) * sizeof(double));
         check_lds((size_t(Da) * Db + size_t(Db) * s) * sizeof(double));
+{
         KTimer _t1("medf_Y2", st,
-                   double(md.drd) * md.db2 * md.dld * (2.0 * Db * Dg * s + 2.0 * f.nHA * Db * s),
+                   double(md.drd) * md.dL * (2.0 * Db * Dg * s * f.chR + 2.0 * f.nHR * Db * s),
                    8.0 * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
-                          double(md.drd) * md.db2 * f.nHA * Db * s));
-        TNB_PT_DISPATCH(pt1, medf_Y2_kernel, dim3(md.drd * md.db2),
-                        (size_t(Db) * Dg + size_t(Dg) * s) * sizeof(double), st, f, conn.p, Db, Dg, X2.p, s, Yf.p);
+                          double(md.drd) * md.db2 * f.nHR * Db * s));
+        TNB_PT_DISPATCH(pt1, medf_Y2_kernel, dim3(md.drd * md.db2 * f.chR),
+                        (size_t(Db) * Dg + size_t(Dg) * s + 16) * sizeof(double), st, f, conn.p, Db, Dg, X2.p, s, Yf.p);
         HIPC(hipGetLastError());
-        KTimer _t2("medf_out", st, double(md.drd) * md.da2 * md.db2 * 2.0 * Da * Db * s,
-                   8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHA * Db * s +
+        }
+{
+        KTimer _t2("medf_out", st, double(md.dR) * md.db2 * 2.0 * Da * Db * s,
+                   8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
                           double(md.dR) * Da * s));
-        TNB_PT_DISPATCH(pt2, medf_out_kernel, dim3(md.drd * md.da2),
+        TNB_PT_DISPATCH(pt2, medf_out_kernel, dim3(md.dR),
                         (size_t(Da) * Db + size_t(Db) * s) * sizeof(double), st, f, A.data.p, Da, Db, Yf.p, s, out);
         HIPC(hipGetLastError());
-      } else {
-        if (double(md.dR) * md.dL > double(1 << 26))
-          fail(TNB_EUNSUPPORTED, "mediating diagram with more than 2^26 (rho, l) pairs");
-        KTimer _t("med_apply", st, double(md.dR) * md.dL * 2.0 * s * Db * double(Dg + Da),
-                  8.0 * (double(md.dL) * Db * Dg + double(md.da2) * md.db2 * Da * Db +
-                         double(md.dld) * md.drd * Dg * s + double(md.dR) * Da * s));
-        hipLaunchKernelGGL(med_apply_kernel, dim3(md.dR), dim3(256), size_t(Db) * s * sizeof(double), st,
-                           md, A.data.p, Da, Db, conn.p, Dg, X2.p, s, out);
-        HIPC(hipGetLastError());
+        }
       }
     }
   }
 
   // D^T Y; Y: (dm*Da) x s, out: (ds*Dg) x s
-  void applyT(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* Yin, int s,
-              double* out) {
+  void applyT_block(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* Yin, int s,
+                    double* out) {
     const int Da = A.dl, Db = A.dr;
     if (k % 2 == 0) {
       const auto& c = g.col[k / 2];
@@ -625,13 +618,16 @@ struct Zipper {
       const uint32_t FREE = full & ~c.Bup;
       const int nfree = 1 << popcount32(FREE);
       double* G = X1.p;  // du x Dg x s
+{
       KTimer _t("site_applyT", st, 2.0 * s * Db * double(Dg + Da) * double(c.du) * nfree,
                 8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
                        double(c.dL) * Da * s + double(c.du) * nfree));
+      allow_big_lds(site_applyT_kernel, size_t(Db) * s * sizeof(double));
       hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
                          k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg,
                          Yin, s, G);
       HIPC(hipGetLastError());
+        }
       // out[v] = sum_u W(v,u) G[u]
       la::gemm(1, c.dv, Dg * s, c.du, la::View{c.Wv, c.Wv_sp, c.Wv_sq, 0}, la::View{G, Dg * s, 1, 0},
                out, int64_t(Dg) * s, 0, 1.0, 0.0, ws, st);
@@ -639,34 +635,29 @@ struct Zipper {
       const auto& md = g.med[(k - 1) / 2];
       double* G2 = X2.p;  // [ld][rd][Dg*s]
       MedF f;
-      if (make_medf(md, &f)) {
+      make_medf(md, &f);
+      {
         ensure(Yf, size_t(md.drd) * md.db2 * f.nHL * Db * s);
         const int pt1 = pick_pt(int64_t(Db) * s), pt2 = pick_pt(int64_t(Dg) * s);
-        check_lds((size_t(Da) * Db + size_t(Da) * s) * sizeof(double));
+        check_lds((size_t(Da) * Db + size_t(Da) * s + 16) * sizeof(double));
         check_lds((size_t(Db) * Dg + size_t(Db) * s) * sizeof(double));
+{
         KTimer _t1("medf_W2", st,
-                   double(md.drd) * md.db2 * md.da2 * (2.0 * Da * Db * s + 2.0 * f.nHL * Db * s),
+                   double(md.dR) * md.db2 * (2.0 * Da * Db * s * f.chL + 2.0 * f.nHL * Db * s),
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
                           double(md.drd) * md.db2 * f.nHL * Db * s));
-        TNB_PT_DISPATCH(pt1, medf_W2_kernel, dim3(md.drd * md.db2),
-                        (size_t(Da) * Db + size_t(Da) * s) * sizeof(double), st, f, A.data.p, Da, Db, Yin, s, Yf.p);
+        TNB_PT_DISPATCH(pt1, medf_W2_kernel, dim3(md.drd * md.db2 * f.chL),
+                        (size_t(Da) * Db + size_t(Da) * s + 16) * sizeof(double), st, f, A.data.p, Da, Db, Yin, s, Yf.p);
         HIPC(hipGetLastError());
-        KTimer _t2("medf_G2", st, double(md.dld) * md.drd * md.db2 * 2.0 * Db * Dg * s,
+        }
+{
+        KTimer _t2("medf_G2", st, double(md.dL) * md.drd * 2.0 * Db * Dg * s,
                    8.0 * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
                           double(md.dld) * md.drd * Dg * s));
         TNB_PT_DISPATCH(pt2, medf_G2_kernel, dim3(md.dld * md.drd),
                         (size_t(Db) * Dg + size_t(Db) * s) * sizeof(double), st, f, conn.p, Db, Dg, Yf.p, s, G2);
         HIPC(hipGetLastError());
-      } else {
-        if (double(md.dR) * md.dL > double(1 << 26))
-          fail(TNB_EUNSUPPORTED, "mediating diagram with more than 2^26 (rho, l) pairs");
-        KTimer _t("med_applyT", st, double(md.dR) * md.dL * 2.0 * s * Db * double(Dg + Da),
-                  8.0 * (double(md.dL) * Db * Dg + double(md.da2) * md.db2 * Da * Db +
-                         double(md.dld) * md.drd * Dg * s + double(md.dR) * Da * s));
-        hipLaunchKernelGGL(med_applyT_kernel, dim3(md.dld * md.drd), dim3(256),
-                           size_t(Db) * s * sizeof(double), st, md, A.data.p, Da, Db, conn.p, Dg, Yin,
-                           s, G2);
-        HIPC(hipGetLastError());
+        }
       }
       // H[ld] (db x Dg*s) = Wdl (db x drd) . G2[ld]
       la::gemm(md.dld, md.db, Dg * s, md.drd, la::View{md.Wdl, md.Wdl_sp, md.Wdl_sq, 0},
@@ -707,8 +698,6 @@ struct Zipper {
       const int t = int(std::min<int64_t>({int64_t(2) * chi, n_rows, n_cols}));
       const bool sketch = n_cols > width;
       const int s = sketch ? width : int(n_cols);
-      if (size_t(A.dr) * s * sizeof(double) > 65536)
-        fail(TNB_EUNSUPPORTED, "diagram tile exceeds 64 KiB of LDS (bond x sketch width too large)");
       // work sizes
       size_t x1n = 0, x2n = 0;
       if (k % 2 == 0) {
@@ -732,17 +721,17 @@ struct Zipper {
       } else {
         hipLaunchKernelGGL(identity_kernel, dim3(blocks(n_cols * n_cols)), dim3(256), 0, st, Om.p, n_cols);
       }
-      apply(g, k, A, Dg, dm, Om.p, s, Y.p);
+      apply_cols<false>(g, k, A, Dg, dm, Om.p, s, Y.p, n_cols, n_rows);
       if (sketch) {
         for (int it = 0; it < o.power_iters; ++it) {
           la::orth(Y.p, n_rows, s, o.cut, Qb.p, ws, st);
-          applyT(g, k, A, Dg, dm, Qb.p, s, Z.p);
+          apply_cols<true>(g, k, A, Dg, dm, Qb.p, s, Z.p, n_rows, n_cols);
           la::orth(Z.p, n_cols, s, o.cut, Qb.p, ws, st);
-          apply(g, k, A, Dg, dm, Qb.p, s, Y.p);
+          apply_cols<false>(g, k, A, Dg, dm, Qb.p, s, Y.p, n_cols, n_rows);
         }
       }
       la::orth(Y.p, n_rows, s, o.cut, Qb.p, ws, st);
-      applyT(g, k, A, Dg, dm, Qb.p, s, Bt.p);
+      apply_cols<true>(g, k, A, Dg, dm, Qb.p, s, Bt.p, n_rows, n_cols);
       // B = Bt^T (s x n_cols): thin SVD through Bt (n_cols x s)
       ensure(Vb, size_t(n_cols) * t);
       ensure(S, size_t(t));
@@ -845,8 +834,8 @@ extern "C" tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opt
     *out = nullptr;
     if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
     if (!opts || opts->chi < 1 || opts->chi > 64 || opts->sketch_extra < 0 || opts->sketch_extra > 64 ||
-        opts->power_iters < 0 || opts->power_iters > 8 || !(opts->cut >= 0.0) || !(opts->cut < 1.0))
-      fail(TNB_EINVAL, "options out of range (1 <= chi <= 64, 0 <= extra <= 64, 0 <= power <= 8, 0 <= cut < 1)");
+        opts->power_iters < 0 || opts->power_iters > 8 || !(opts->cut >= 1e-7) || !(opts->cut < 1.0))
+      fail(TNB_EINVAL, "options out of range (1 <= chi <= 64, 0 <= extra <= 64, 0 <= power <= 8, 1e-7 <= cut < 1)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     auto env = std::make_unique<tnb_env>();
     env->cl = cl;

@@ -15,7 +15,7 @@ struct View {
 
 // Reusable device scratch (grows, never shrinks).
 struct Scratch {
-  DevBuf<double> buf[6];
+  DevBuf<double> buf[9];
   double* get(int slot, size_t n) {
     if (buf[slot].n < n) buf[slot].alloc(n + n / 4 + 64);
     return buf[slot].p;
@@ -34,14 +34,16 @@ void gemm(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t
 void eigh(double* G, int s, double* V, double* lam, hipStream_t st);
 
 // Orthonormal basis of the numerical range of Y (n x s, row-major): Q (n x s)
-// holds the directions with singular value > cut * largest, remaining
-// columns zero.  Two Gram passes (the second re-orthonormalises).
+// holds the left singular vectors with singular value > cut * largest,
+// remaining columns zero (accurate thin SVD, see thin_svd_tall).
 void orth(const double* Y, int64_t n, int s, double cut, double* Q, Scratch& ws, hipStream_t st);
 
-// Thin SVD through the Gram matrix of a tall M (n x m): keeps t = min(tmax, m)
-// singular triplets, dropping sigma <= cut * sigma_max (set to 0).
-//   U  (n x t) = M V S^-1 (zero columns for dropped)   [if U != nullptr]
-//   S  (t), VT (t x m) = V^T rows.
+// Thin SVD of a tall M (n x m, m <= 1000): M = U S V^T with the leading t
+// triplets kept and sigma <= cut * sigma_max set to 0 (with their vectors).
+// A Gram pass gives an orthonormal basis Q of range(M); R = Q^T M is then
+// decomposed by one-sided Jacobi, so singular values carry errors of order
+// eps * sigma_max, as with a Householder-based SVD.
+//   U (n x t) [if not null], S (t), VT (t x m).
 void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double* U, double* S,
                    double* VT, Scratch& ws, hipStream_t st);
 

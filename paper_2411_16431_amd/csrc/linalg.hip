@@ -67,11 +67,13 @@ static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double
   const int64_t per = int64_t(M) * N;
   double* P = ws.get(5, size_t(per * batch * nchunk));
   dim3 grid(unsigned(tiles2d), unsigned(batch * nchunk));
+  {
   KTimer _t("gemm", s, 2.0 * M * double(N) * double(K) * batch,
             8.0 * (double(M) * K + double(K) * N + double(M) * N) * batch);
   hipLaunchKernelGGL(gemm_kernel, grid, dim3(TILE, TILE), 0, s, M, N, K, kchunk, A.p, A.rs, A.cs,
                      A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
   HIPC(hipGetLastError());
+  }
   const int64_t tot = per * batch;
   hipLaunchKernelGGL(gemm_finish_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s, batch,
                      M, N, int(nchunk), P, per * batch, per, C, ldc, bsc, alpha, beta);
@@ -216,54 +218,203 @@ __global__ void inv_sqrt_weights_kernel(const double* __restrict__ V, const doub
   W[idx] = (l0 > 0.0 && l > rel * l0) ? V[idx] / sqrt(l) : 0.0;
 }
 
-void orth(const double* Y, int64_t n, int s, double cut, double* Q, Scratch& ws, hipStream_t st) {
-  double* G = ws.get(0, size_t(s) * s);
-  double* V = ws.get(1, size_t(s) * s);
-  double* lam = ws.get(2, size_t(s));
-  double* W = ws.get(3, size_t(s) * s);
-  double* T = ws.get(4, size_t(n) * s);
-  // pass 1: Q1 = Y V L^-1/2 over the kept directions
-  gemm(1, s, s, n, View{Y, 1, s, 0}, View{Y, s, 1, 0}, G, s, 0, 1.0, 0.0, ws, st);
-  eigh(G, s, V, lam, st);
-  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((s * s + 255) / 256), dim3(256), 0, st, V, lam, s,
-                     cut * cut, W);
-  gemm(1, int(n), s, s, View{Y, s, 1, 0}, View{W, s, 1, 0}, T, s, 0, 1.0, 0.0, ws, st);
-  // pass 2: re-orthonormalise (eigenvalues ~1 for kept, 0 for padding)
-  gemm(1, s, s, n, View{T, 1, s, 0}, View{T, s, 1, 0}, G, s, 0, 1.0, 0.0, ws, st);
-  eigh(G, s, V, lam, st);
-  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((s * s + 255) / 256), dim3(256), 0, st, V, lam, s,
-                     0.25, W);
-  gemm(1, int(n), s, s, View{T, s, 1, 0}, View{W, s, 1, 0}, Q, s, 0, 1.0, 0.0, ws, st);
+// One-sided Jacobi SVD (Hestenes; Golub & Van Loan Sec. 8.6.3) of a small
+// m x m matrix A (row-major, overwritten by U*S): rotations orthogonalise the
+// columns pairwise, round-robin over disjoint pairs.  Singular values are
+// accurate to eps * sigma_max.  Outputs sorted descending: S[m], U (m x m,
+// columns of A normalised; zero for sigma = 0), V (m x m).
+__global__ void __launch_bounds__(1024) hestenes_kernel(double* __restrict__ A, int m, double* __restrict__ U,
+                                                        double* __restrict__ V, double* __restrict__ S) {
+  extern __shared__ double sh[];
+  double* cs = sh;           // [512]
+  double* sn = sh + 512;     // [512]
+  int* pp = reinterpret_cast<int*>(sh + 1024);
+  int* qq = pp + 512;
+  double* red = sh + 1536;   // [1024]
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int mm = m + (m & 1);
+  for (int idx = tid; idx < m * m; idx += nt) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double worst = 0.0;
+    for (int round = 0; round < mm - 1; ++round) {
+      for (int a = tid; a < mm / 2; a += nt) {
+        int p1 = (a == 0) ? 0 : 1 + (a - 1 + round) % (mm - 1);
+        int p2 = 1 + (mm - 2 - a + round) % (mm - 1);
+        int p = p1 < p2 ? p1 : p2, q = p1 < p2 ? p2 : p1;
+        double c = 1.0, sv = 0.0;
+        if (q < m) {
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = 0; i < m; ++i) {
+            const double x = A[i * m + p], y = A[i * m + q];
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
+          }
+          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sv = c * t;
+            const double r = fabs(ga) / sqrt(al * be);
+            worst = fmax(worst, r);
+          }
+        }
+        pp[a] = p;
+        qq[a] = q;
+        cs[a] = c;
+        sn[a] = sv;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < (mm / 2) * m; idx += nt) {
+        const int a = idx / m, i = idx % m;
+        const int p = pp[a], q = qq[a];
+        if (q >= m || sn[a] == 0.0) continue;
+        const double x = A[i * m + p], y = A[i * m + q];
+        A[i * m + p] = cs[a] * x - sn[a] * y;
+        A[i * m + q] = sn[a] * x + cs[a] * y;
+        const double vx = V[i * m + p], vy = V[i * m + q];
+        V[i * m + p] = cs[a] * vx - sn[a] * vy;
+        V[i * m + q] = sn[a] * vx + cs[a] * vy;
+      }
+      __syncthreads();
+    }
+    red[tid] = worst;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    const bool done = red[0] <= 1e-15;
+    __syncthreads();
+    if (done) break;
+  }
+  // column norms, sort descending (ties by index), normalise
+  double* nrm = red;
+  for (int j = tid; j < m; j += nt) {
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i) acc = fma(A[i * m + j], A[i * m + j], acc);
+    nrm[j] = sqrt(acc);
+  }
+  __syncthreads();
+  int* rank = reinterpret_cast<int*>(cs);
+  for (int j = tid; j < m; j += nt) {
+    int r = 0;
+    for (int o = 0; o < m; ++o) r += (nrm[o] > nrm[j]) || (nrm[o] == nrm[j] && o < j);
+    rank[j] = r;
+  }
+  __syncthreads();
+  for (int j = tid; j < m; j += nt) S[rank[j]] = nrm[j];
+  for (int idx = tid; idx < m * m; idx += nt) {
+    const int i = idx / m, j = idx % m;
+    U[i * m + rank[j]] = nrm[j] > 0.0 ? A[idx] / nrm[j] : 0.0;
+  }
+  __syncthreads();
+  // V columns permuted through A as scratch
+  for (int idx = tid; idx < m * m; idx += nt) A[idx] = V[idx];
+  __syncthreads();
+  for (int idx = tid; idx < m * m; idx += nt) {
+    const int i = idx / m, j = idx % m;
+    V[i * m + rank[j]] = A[idx];
+  }
 }
 
-// S[i] = sqrt(lam[i]) (0 if dropped), Winv = V[:, :t] / S (0 if dropped),
-// VT = V[:, :t]^T (zero rows if dropped).
-__global__ void svd_factors_kernel(const double* __restrict__ V, const double* __restrict__ lam,
-                                   int m, int t, double rel, double* __restrict__ S,
-                                   double* __restrict__ Winv, double* __restrict__ VT) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m * t) return;
-  const int row = idx / t, col = idx % t;
-  const double l0 = lam[0], l = lam[col];
-  const bool keep = l0 > 0.0 && l > rel * l0;
-  const double sig = keep ? sqrt(l) : 0.0;
-  if (row == 0) S[col] = sig;
-  Winv[idx] = keep ? V[row * m + col] / sig : 0.0;
-  if (VT) VT[col * m + row] = keep ? V[row * m + col] : 0.0;
+static void hestenes(double* A, int m, double* U, double* V, double* S, hipStream_t st) {
+  if (m > 1000) fail(TNB_EUNSUPPORTED, "SVD limited to 1000 x 1000");
+  KTimer _t("svd_small", st, 0.0, 24.0 * m * m);
+  hipLaunchKernelGGL(hestenes_kernel, dim3(1), dim3(1024), 2560 * sizeof(double), st, A, m, U, V, S);
+  HIPC(hipGetLastError());
+}
+
+// Accurate thin SVD of a tall n x m matrix M (m small):
+//   (1) Gram/eigen pass -> nearly orthonormal basis Q1 of range(M),
+//   (2) Gram/eigen pass on Q1 -> orthonormal Q (zero columns where empty),
+//   (3) R = Q^T M by GEMM, (4) one-sided Jacobi SVD R = U_R S V_R^T,
+//   (5) M = (Q U_R) S V_R^T.
+// Singular values above 1e-7 * sigma_max carry errors of order
+// eps * sigma_max, as with a Householder-based SVD; step (1) works on
+// squared values and only keeps directions above sigma_max * 1e-7.
+// Outputs: Uo (n x m) = Q U_R, S (m, descending), Vo (m x m) = V_R.
+static void tall_svd(const double* M, int64_t n, int m, double* Uo, double* S, double* Vo, Scratch& ws,
+                     hipStream_t st) {
+  double* G = ws.get(0, size_t(m) * m);
+  double* V = ws.get(1, size_t(m) * m);
+  double* lam = ws.get(2, size_t(m));
+  double* W = ws.get(3, size_t(m) * m);
+  double* Q1 = ws.get(4, size_t(n) * m);
+  gemm(1, m, m, n, View{M, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  eigh(G, m, V, lam, st);
+  // pass 1 keeps eigen-directions down to lambda/lambda_max = 1e-14 (sigma
+  // ratio 1e-7): below that, Gram eigenvectors are noise and scaling them by
+  // 1/sqrt(lambda) would swamp the second pass.  Rank decisions are made later
+  // on accurate singular values, at cut >= 1e-7 in sigma.
+  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st, V, lam, m,
+                     1e-14, W);
+  gemm(1, int(n), m, m, View{M, m, 1, 0}, View{W, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
+  gemm(1, m, m, n, View{Q1, 1, m, 0}, View{Q1, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  eigh(G, m, V, lam, st);
+  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st, V, lam, m,
+                     0.25, W);
+  // Q (into Uo) = Q1 W
+  gemm(1, int(n), m, m, View{Q1, m, 1, 0}, View{W, m, 1, 0}, Uo, m, 0, 1.0, 0.0, ws, st);
+  // R = Q^T M  (m x m) into G
+  gemm(1, m, m, n, View{Uo, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  double* UR = W;  // reuse
+  hestenes(G, m, UR, Vo, S, st);
+  // Uo <- Q U_R  (through Q1 as scratch)
+  gemm(1, int(n), m, m, View{Uo, m, 1, 0}, View{UR, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
+  HIPC(hipMemcpyAsync(Uo, Q1, size_t(n) * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+// keep columns j with S[j] > cut * S[0]: Q[:, j] = U[:, j] (else 0)
+__global__ void keep_cols_kernel(const double* __restrict__ U, const double* __restrict__ S, int64_t n, int m,
+                                 double cut, double* __restrict__ Q) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n * m) return;
+  const int j = int(idx % m);
+  Q[idx] = (S[0] > 0.0 && S[j] > cut * S[0]) ? U[idx] : 0.0;
+}
+
+void orth(const double* Y, int64_t n, int s, double cut, double* Q, Scratch& ws, hipStream_t st) {
+  double* Ub = ws.get(6, size_t(n) * s);
+  double* Sb = ws.get(7, size_t(s));
+  double* Vb = ws.get(8, size_t(s) * s);
+  tall_svd(Y, n, s, Ub, Sb, Vb, ws, st);
+  hipLaunchKernelGGL(keep_cols_kernel, dim3(unsigned((int64_t(n) * s + 255) / 256)), dim3(256), 0, st, Ub,
+                     Sb, int64_t(n), s, cut, Q);
+  HIPC(hipGetLastError());
+}
+
+// S[i] (0 if dropped), Uo columns zeroed if dropped, VT = V[:, :t]^T (zero rows if dropped)
+__global__ void svd_trunc_kernel(double* __restrict__ U, int64_t n, int m, int t, double cut,
+                                 const double* __restrict__ Sfull, const double* __restrict__ V,
+                                 double* __restrict__ Uout, double* __restrict__ S, double* __restrict__ VT) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool first = idx < int64_t(t) * m;
+  if (first) {
+    const int i = int(idx / m), col = int(idx % m);
+    const bool keep = Sfull[0] > 0.0 && Sfull[i] > cut * Sfull[0];
+    VT[idx] = keep ? V[col * m + i] : 0.0;
+    if (col == 0) S[i] = keep ? Sfull[i] : 0.0;
+  }
+  if (Uout && idx < n * t) {
+    const int64_t r = idx / t;
+    const int j = int(idx % t);
+    const bool keep = Sfull[0] > 0.0 && Sfull[j] > cut * Sfull[0];
+    Uout[idx] = keep ? U[r * m + j] : 0.0;
+  }
 }
 
 void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double* U, double* S,
                    double* VT, Scratch& ws, hipStream_t st) {
-  double* G = ws.get(0, size_t(m) * m);
-  double* V = ws.get(1, size_t(m) * m);
-  double* lam = ws.get(2, size_t(m));
-  double* Winv = ws.get(3, size_t(m) * t);
-  gemm(1, m, m, n, View{M, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
-  eigh(G, m, V, lam, st);
-  hipLaunchKernelGGL(svd_factors_kernel, dim3((m * t + 255) / 256), dim3(256), 0, st, V, lam, m, t,
-                     cut * cut, S, Winv, VT);
+  double* Ub = ws.get(6, size_t(n) * m);
+  double* Sb = ws.get(7, size_t(m));
+  double* Vb = ws.get(8, size_t(m) * m);
+  tall_svd(M, n, m, Ub, Sb, Vb, ws, st);
+  const int64_t tot = std::max<int64_t>(int64_t(n) * t, int64_t(t) * m);
+  hipLaunchKernelGGL(svd_trunc_kernel, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, st, Ub, int64_t(n), m, t,
+                     cut, Sb, Vb, U, S, VT);
   HIPC(hipGetLastError());
-  if (U) gemm(1, int(n), t, m, View{M, m, 1, 0}, View{Winv, t, 1, 0}, U, t, 0, 1.0, 0.0, ws, st);
 }
 
 }  // namespace la

@@ -49,11 +49,38 @@ def test_stepwise_beam_matches_oracle(kind, kw, chi, M):
         assert np.allclose(logp.cpu().numpy(), rec["logp"], rtol=1e-6, atol=1e-6)
 
 
+@pytest.mark.parametrize("chi", [16, 64])
+def test_stepwise_beam_zephyr_t4_planted(chi):
+    # t = 4 cells (12 spins here, d = 4096) on sparse planted couplings, where the
+    # truncation is exact and parity well posed; every step compared
+    pk, torch = _gpu()
+    from tnb_inputs.rng import uniform01
+    inst, s, E0 = planted_loops(1, 4, 77, loops_per_cell=2)
+    # small fields break the exact ties between uncoupled spins (h = 0 leaves many
+    # equally probable candidates, whose order only rounding would decide)
+    inst.h = 0.1 * (2 * uniform01(77, inst.n_spins, stream=2) - 1)
+    ora_env = contract_env(inst, 1.0, Options(chi=chi, power=2, seed=5, cut=1e-7))
+    ref = solve(inst, 1.0, ora_env, M=16, K=4, trace=True)
+    env = pk.Env(pk.Clusters(inst, 1.0), pk.EnvOptions(chi=chi, power_iters=2, seed=5, cut=1e-7))
+    beam = pk.Beam(env, 16)
+    from oracle.potts import Potts
+    P = Potts(inst)
+    for rec in ref["steps"]:
+        p = beam.marginals().cpu().numpy()
+        assert np.abs(p - rec["p"]).max() <= 1e-8
+        beam.step()
+        states, logp = beam.export(16, inst.n_spins)
+        S = states.cpu().numpy()
+        got_X = P.cluster_of_states(np.where(S == 0, -1, S))[:, : rec["n"] + 1]
+        assert np.array_equal(got_X, rec["X"][:, : rec["n"] + 1])
+        assert np.allclose(logp.cpu().numpy(), rec["logp"], rtol=1e-9, atol=1e-9)
+
+
 @pytest.mark.parametrize("kind,kw", [("king", dict(R=3, C=3, a=1)), ("king", dict(R=2, C=2, a=2))])
 def test_exact_search_finds_ground_state(kind, kw):
     pk, torch = _gpu()
     inst = make_instance(kind, 302, jdist="uniform", hdist="uniform0.1", **kw)
-    res = pk.solve(inst, 2.0, chi=64, M=4096, K=2, cut=1e-13)
+    res = pk.solve(inst, 2.0, chi=64, M=4096, K=2, cut=1e-7)
     bf = ising.brute_force(inst, 2.0)
     assert abs(res["energies"][0] - bf["E_min"]) < 1e-12
     assert np.array_equal(res["energies"], ising.energies(inst, res["states"]))
