@@ -129,8 +129,10 @@ tnb_status tnb_beam_info(const tnb_beam* beam, int32_t* step, int32_t* n_parents
 
 /* Conditional marginals p(x_{n+1} | boundary of parent b) for every parent
  * of the current step (Eq. 7, 9; Fig. 6b): d_out (device) receives
- * [n_parents][d] probabilities, normalised per parent, non-positive
- * contractions clipped to 0.  out_len must be >= n_parents*d.
+ * [n_parents][d] probabilities, normalised per parent.  The marginal is a
+ * ratio of contractions of one network, so a common sign of the approximate
+ * environment cancels: entries are taken with the sign of their sum, and
+ * those left non-positive are clipped to 0.  out_len must be >= n_parents*d.
  * Errors: TNB_EINVAL (size), TNB_ENUMERIC (a parent with no positive
  * marginal; it is reported, not dropped, by this call). */
 tnb_status tnb_marginals(tnb_beam* beam, double* d_out, int64_t out_len, tnb_stream stream);

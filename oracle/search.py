@@ -149,7 +149,12 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
             n = r * C + c
             last = (n == ncell - 1)
             q, vec = marginals(net, env, r, c, X, L, Rrow[c][rid])
-            qpos = np.where(q > 0, q, 0.0)
+            # Eq. (9) is a ratio of two contractions of the same network, so a
+            # common sign of the approximate environment cancels: entries are
+            # taken with the sign of their sum, and those left non-positive get
+            # probability 0 (R9).
+            sgn = np.where(q.sum(axis=1, keepdims=True) < 0, -1.0, 1.0)
+            qpos = np.where(q * sgn > 0, q * sgn, 0.0)
             Zb = qpos.sum(axis=1)
             alive = Zb > 0
             with np.errstate(divide="ignore"):

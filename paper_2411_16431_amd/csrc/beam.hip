@@ -246,14 +246,27 @@ __global__ void beam_q_kernel(BCol c, int has_left, int left_cell, const int32_t
   q[idx] = g * acc;
 }
 
-// per parent: Z_b = sum q+ ; score[b][x] = logp_b + log(q+) - log(Z_b) (or -inf)
+// per parent: the marginal is a ratio of contractions of one network, so the
+// common sign of the approximate environment cancels: sg = sign(sum q),
+// Z_b = sum of the positive entries of sg*q, score = logp_b + log(sg*q) - log Z_b
+// (entries with sg*q <= 0 get probability 0 and score -inf).
 __global__ void beam_score_kernel(const double* __restrict__ q, int64_t d, const double* __restrict__ logp,
                                   double* __restrict__ score, double* __restrict__ prob, int* __restrict__ dead) {
   __shared__ double red[256];
   const int b = blockIdx.x;
   double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < d; i += blockDim.x) acc += q[b * d + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sg = red[0] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
+  acc = 0.0;
   for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
-    const double v = q[b * d + i];
+    const double v = sg * q[b * d + i];
     acc += v > 0.0 ? v : 0.0;
   }
   red[threadIdx.x] = acc;
@@ -267,7 +280,7 @@ __global__ void beam_score_kernel(const double* __restrict__ q, int64_t d, const
   if (threadIdx.x == 0 && !alive) dead[0] = 1;
   const double lZ = alive ? log(Z) : 0.0;
   for (int64_t i = threadIdx.x; i < d; i += blockDim.x) {
-    const double v = q[b * d + i];
+    const double v = sg * q[b * d + i];
     const bool ok = alive && v > 0.0;
     if (score) score[b * d + i] = ok ? logp[b] + (log(v) - lZ) : -INFINITY;
     if (prob) prob[b * d + i] = ok ? v / Z : 0.0;
@@ -648,6 +661,20 @@ extern "C" tnb_status tnb_marginals(tnb_beam* bm, double* d_out, int64_t out_len
     const int64_t d = int64_t(1) << bm->env->cl->lat.k[bm->step];
     if (!d_out || out_len < bm->npar * d) fail(TNB_EINVAL, "output too small");
     compute_q(bm, st);
+    if (std::getenv("TNB_DEBUG")) {
+      std::vector<double> hq(std::min<int64_t>(d, 4));
+      HIPC(hipMemcpy(hq.data(), bm->q.p, hq.size() * sizeof(double), hipMemcpyDeviceToHost));
+      std::fprintf(stderr, "[tnb] step %d q[0][0..] =", bm->step);
+      for (double v : hq) std::fprintf(stderr, " %.6e", v);
+      std::fprintf(stderr, "\n");
+      for (int c = bm->env->cl->lat.C - 1; c >= 0; --c) {
+        std::vector<double> hr(std::min<size_t>(bm->R[c].n, 6));
+        HIPC(hipMemcpy(hr.data(), bm->R[c].p, hr.size() * sizeof(double), hipMemcpyDeviceToHost));
+        std::fprintf(stderr, "[tnb]   R[%d] (%zu entries) head:", c, bm->R[c].n);
+        for (double v : hr) std::fprintf(stderr, " %.3e", v);
+        std::fprintf(stderr, "\n");
+      }
+    }
     HIPC(hipMemsetAsync(bm->dead.p, 0, sizeof(int), st));
     hipLaunchKernelGGL(beam_score_kernel, dim3(bm->npar), dim3(256), 0, st, bm->q.p, d, bm->logp.p, nullptr, d_out,
                        bm->dead.p);

@@ -11,6 +11,8 @@
 //   mediating^T G2[l_d][rho_d] = sum_{rho in rho_d, l in l_d} Wh K[l]^T A[..]^T Y[rho]
 // The mediating sums are evaluated in the factored order described below.
 // Each output block is owned by one workgroup (no atomics: deterministic).
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 
 #include "env.h"
@@ -874,6 +876,9 @@ extern "C" tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opt
       val *= v;
     }
     if (!(val != 0.0) || !std::isfinite(val)) fail(TNB_ENUMERIC, "partition function vanished");
+    if (std::getenv("TNB_DEBUG"))
+      std::fprintf(stderr, "[tnb] top contraction value %.6e (sign %+d), ln0 %.6f, lam1 %.6f\n", val,
+                   val > 0 ? 1 : -1, ln0, env->psi[1].logscale);
     env->logZ = cl->shift + env->psi[1].logscale + ln0 + std::log(std::fabs(val));
     if (log_z) *log_z = env->logZ;
     HIPC(hipStreamSynchronize(st));

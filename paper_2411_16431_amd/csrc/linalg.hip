@@ -326,35 +326,63 @@ static void hestenes(double* A, int m, double* U, double* V, double* S, hipStrea
   HIPC(hipGetLastError());
 }
 
+// Wn[:, j] = V[:, j] for lam_j > rel * lam_0 (unscaled), else 0
+__global__ void keep_weights_kernel(const double* __restrict__ V, const double* __restrict__ lam, int m,
+                                    double rel, double* __restrict__ W) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int col = idx % m;
+  W[idx] = (lam[0] > 0.0 && lam[col] > rel * lam[0]) ? V[idx] : 0.0;
+}
+
+// dinv[j] = 1/sqrt(G[j][j]) (0 for an empty column); G <- D^-1/2 G D^-1/2
+__global__ void normalise_gram_kernel(double* __restrict__ G, int m, double* __restrict__ dinv) {
+  __shared__ double d[1024];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) d[j] = G[j * m + j] > 0.0 ? 1.0 / sqrt(G[j * m + j]) : 0.0;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) G[idx] *= d[idx / m] * d[idx % m];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) dinv[j] = d[j];
+}
+
+// W2[i][j] = dinv[i] V2[i][j] / sqrt(lam2[j]) for lam2[j] > thr (absolute), else 0
+__global__ void ortho_weights_kernel(const double* __restrict__ V2, const double* __restrict__ lam2,
+                                     const double* __restrict__ dinv, int m, double thr, double* __restrict__ W) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m) return;
+  const int i = idx / m, j = idx % m;
+  W[idx] = lam2[j] > thr ? dinv[i] * V2[idx] / sqrt(lam2[j]) : 0.0;
+}
+
 // Accurate thin SVD of a tall n x m matrix M (m small):
-//   (1) Gram/eigen pass -> nearly orthonormal basis Q1 of range(M),
-//   (2) Gram/eigen pass on Q1 -> orthonormal Q (zero columns where empty),
+//   (1) eigenvectors V of the Gram matrix M^T M, kept down to
+//       lambda/lambda_max = 1e-14 (sigma ratio 1e-7): Q1 = M V,
+//   (2) Q1's columns scaled to unit norm (measured, not 1/sqrt(lambda), which
+//       is unreliable for small lambda), their Gram matrix diagonalised, and
+//       Q = Q1 D^-1/2 V2 L2^-1/2 over eigenvalues above 1e-6 (orthonormal),
 //   (3) R = Q^T M by GEMM, (4) one-sided Jacobi SVD R = U_R S V_R^T,
 //   (5) M = (Q U_R) S V_R^T.
 // Singular values above 1e-7 * sigma_max carry errors of order
-// eps * sigma_max, as with a Householder-based SVD; step (1) works on
-// squared values and only keeps directions above sigma_max * 1e-7.
+// eps * sigma_max, as with a Householder-based SVD.
 // Outputs: Uo (n x m) = Q U_R, S (m, descending), Vo (m x m) = V_R.
 static void tall_svd(const double* M, int64_t n, int m, double* Uo, double* S, double* Vo, Scratch& ws,
                      hipStream_t st) {
+  if (m > 1024) fail(TNB_EUNSUPPORTED, "thin SVD limited to 1024 columns");
   double* G = ws.get(0, size_t(m) * m);
   double* V = ws.get(1, size_t(m) * m);
-  double* lam = ws.get(2, size_t(m));
+  double* lam = ws.get(2, size_t(m) + size_t(m));  // lam and dinv
+  double* dinv = lam + m;
   double* W = ws.get(3, size_t(m) * m);
   double* Q1 = ws.get(4, size_t(n) * m);
+  const unsigned gb = unsigned((m * m + 255) / 256);
   gemm(1, m, m, n, View{M, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
   eigh(G, m, V, lam, st);
-  // pass 1 keeps eigen-directions down to lambda/lambda_max = 1e-14 (sigma
-  // ratio 1e-7): below that, Gram eigenvectors are noise and scaling them by
-  // 1/sqrt(lambda) would swamp the second pass.  Rank decisions are made later
-  // on accurate singular values, at cut >= 1e-7 in sigma.
-  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st, V, lam, m,
-                     1e-14, W);
+  hipLaunchKernelGGL(keep_weights_kernel, dim3(gb), dim3(256), 0, st, V, lam, m, 1e-14, W);
   gemm(1, int(n), m, m, View{M, m, 1, 0}, View{W, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
   gemm(1, m, m, n, View{Q1, 1, m, 0}, View{Q1, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  hipLaunchKernelGGL(normalise_gram_kernel, dim3(1), dim3(256), 0, st, G, m, dinv);
   eigh(G, m, V, lam, st);
-  hipLaunchKernelGGL(inv_sqrt_weights_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st, V, lam, m,
-                     0.25, W);
+  hipLaunchKernelGGL(ortho_weights_kernel, dim3(gb), dim3(256), 0, st, V, lam, dinv, m, 1e-6, W);
+  HIPC(hipGetLastError());
   // Q (into Uo) = Q1 W
   gemm(1, int(n), m, m, View{Q1, m, 1, 0}, View{W, m, 1, 0}, Uo, m, 0, 1.0, 0.0, ws, st);
   // R = Q^T M  (m x m) into G
