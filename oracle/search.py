@@ -197,6 +197,8 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
             Ln = vec[bb[keep], xx[keep]]
             nrm = np.abs(Ln).max(axis=1, keepdims=True)
             Ln = Ln / np.where(nrm > 0, nrm, 1.0)
+            if trace:
+                rec["L"] = Ln.copy()
             rid = rid[bb[keep]]
             X, logp, L = Xn, sc[keep], Ln
     states = net.P.states_of_clusters(X)
@@ -223,3 +225,129 @@ def root_marginal_check(net, env):
     Rrow = right_envs(net, env, 0, X)
     q, _ = marginals(net, env, 0, 0, X, np.ones((1, 1)), Rrow[0])
     return q
+
+
+def _row_contract(net, env, r, c, xb, lvec, clamp):
+    """Contract the free clusters c..C-1 of row r with Psi_{r+1} for one parent.
+
+    xb: the parent's cluster values (row r-1 and row-r columns < c fixed);
+    lvec: its left vector (over the bond left of Psi site 2c-1); clamp:
+    {cell: allowed boolean mask over x} restricting free clusters.  Returns
+    (sign, log|Z|).  Plain left-to-right transfer over the full configuration
+    of the previous cluster.
+    """
+    psi, cols = _row_data(net, env, r)
+    C = net.C
+    logs = 0.0
+    # state: S[beta, x_prev] with x_prev the previous cluster's full value
+    if c == 0:
+        S = np.ones((1, 1))
+        prev_vals = np.zeros(1, dtype=np.int64)
+    else:
+        S = lvec.reshape(-1, 1)
+        prev_vals = np.array([xb[net.cell(r, c - 1)]], dtype=np.int64)
+    for cc in range(c, C):
+        d = cols[cc]
+        n = d["n"]
+        x = d["x"]
+        g = d["w"] * _phi(net, r, cc, xb[None, :])[0]
+        if n in clamp:
+            g = g * clamp[n]
+        A2c = psi[2 * cc]
+        newS = np.zeros((A2c.shape[2], len(x)))
+        if cc == 0:
+            vec = A2c[0][d["vd"], :]                                      # (x, D)
+            newS = (g[:, None] * vec).T
+        else:
+            nl = net.cell(r, cc - 1)
+            A2m = psi[2 * cc - 1]
+            Wh = net.Wt(nl, n)
+            for ip, xp in enumerate(prev_vals):
+                if not np.any(S[:, ip]):
+                    continue
+                ap = pext(np.array([xp]), net.B(nl, net.cell(r + 1, cc)))[0]
+                hp = pext(np.array([xp]), net.B(nl, n))[0]
+                sig = ap + d["da2"] * d["bd"]                                # (x,)
+                T = np.einsum("a,xag->xg", S[:, ip], np.transpose(A2m[:, sig, :], (1, 0, 2)))
+                vec = np.einsum("xg,gxe->xe", T, A2c[:, d["vd"], :])
+                newS += (g * Wh[hp, d["xh"]])[None, :] * vec.T
+        mx = np.abs(newS).max()
+        if mx == 0:
+            return 0.0, -np.inf
+        S = newS / mx
+        logs += np.log(mx)
+        prev_vals = x
+    tot = S.sum()
+    return (1.0 if tot > 0 else -1.0), logs + np.log(abs(tot))
+
+
+def row_spins_edges(net, r, c):
+    """Spins of the unfixed clusters c..C-1 of row r (cluster by cluster,
+    ascending) and the couplings with both ends in one of those clusters."""
+    P = net.P
+    spins, edges = [], []
+    for cc in range(c, net.C):
+        n = net.cell(r, cc)
+        spins.extend(P.spins[n].tolist())
+        edges.extend(P.intra[n])
+    return np.array(spins, dtype=np.int64), np.array(edges, dtype=np.int64)
+
+
+def row_moments(net, env, r, c, Xpar, L):
+    """<s_i>_b and <s_i s_j>_b over the unfixed clusters c..C-1 of row r, for
+    every parent b (rows of Xpar, left vectors L), with Psi_{r+1} fixed.
+
+    Definition by clamping: <s_i>_b = (Z_b(s_i=+1) - Z_b(s_i=-1)) / Z_b and
+    <s_i s_j>_b = (Z_b(s_i s_j=+1) - Z_b(s_i s_j=-1)) / Z_b, every Z_b a full
+    contraction of the conditioned network of Fig. 6(b) (Eq. 10).  These are
+    -1/beta d log Z_b / d h_i and -1/beta d log Z_b / d J_ij.  The values are
+    signed ratios of the approximate contraction: no clipping is applied, so
+    they are exact derivatives of log|Z_b| even where the approximate
+    environment produces negative terms.  Returns (m1 [npar, spins],
+    m2 [npar, edges], spins, edges).
+    """
+    P = net.P
+    inst = P.inst
+    spins, edges = row_spins_edges(net, r, c)
+    m1 = np.zeros((Xpar.shape[0], len(spins)))
+    m2 = np.zeros((Xpar.shape[0], len(edges)))
+
+    def ratio(b, clamps):
+        vals = []
+        for cl in clamps:
+            sg, lz = _row_contract(net, env, r, c, Xpar[b], L[b], cl)
+            vals.append((sg, lz))
+        return vals
+
+    for b in range(Xpar.shape[0]):
+        for col, i in enumerate(spins):
+            n = int(net.P.inst.cell_of[i])
+            x = np.arange(1 << int(P.k[n]))
+            up = ((x >> P.bit[i]) & 1).astype(float)
+            (sp, lp), (sm, lm) = ratio(b, [{n: up}, {n: 1.0 - up}])
+            top = max(lp, lm)
+            zp = sp * np.exp(lp - top) if np.isfinite(lp) else 0.0
+            zm = sm * np.exp(lm - top) if np.isfinite(lm) else 0.0
+            m1[b, col] = (zp - zm) / (zp + zm)
+        for col, e in enumerate(edges):
+            i, j = inst.edges[e]
+            n = int(inst.cell_of[i])
+            x = np.arange(1 << int(P.k[n]))
+            par = (((x >> P.bit[i]) ^ (x >> P.bit[j])) & 1) == 0
+            (sp, lp), (sm, lm) = ratio(b, [{n: par.astype(float)}, {n: (~par).astype(float)}])
+            top = max(lp, lm)
+            zp = sp * np.exp(lp - top) if np.isfinite(lp) else 0.0
+            zm = sm * np.exp(lm - top) if np.isfinite(lm) else 0.0
+            m2[b, col] = (zp - zm) / (zp + zm)
+    return m1, m2, spins, edges
+
+
+def row_logz(net, env, r, c, xb, lvec):
+    """log|Z_b| of the conditioned row network including the local log-scales
+    of the unfixed clusters (the -beta * min E_n of Eq. 6), so that finite
+    differences in h or J of a row-r spin are taken on the true log Z_b up
+    to terms that do not depend on them."""
+    sg, lz = _row_contract(net, env, r, c, xb, lvec, {})
+    for cc in range(c, net.C):
+        lz += -net.beta * net.P.local_energy(net.cell(r, cc)).min()
+    return lz

@@ -98,3 +98,124 @@ def test_planted_small_instance_reaches_planted_energy():
     bf = ising.brute_force(inst, 1.0)
     assert abs(bf["E_min"] - E0) < 1e-12        # the planted energy is the ground energy
     assert abs(res["energies"][0] - E0) < 1e-12
+
+
+# ---- row moments (adjoint of the row contraction) -------------------------
+
+from oracle.search import row_moments, row_logz, row_spins_edges  # noqa: E402
+from oracle.bmps import Network as _Net  # noqa: E402
+
+
+def _cond_brute(inst, beta, fixed, spins, edges):
+    """<s_i>, <s_i s_j> given fixed spins {i: +-1}, by enumerating the rest."""
+    N = inst.n_spins
+    free = np.array([i for i in range(N) if i not in fixed], dtype=np.int64)
+    x = np.arange(1 << len(free))
+    s = np.zeros((len(x), N))
+    for i, v in fixed.items():
+        s[:, i] = v
+    s[:, free] = ((x[:, None] >> np.arange(len(free))) & 1) * 2 - 1
+    E = (s[:, inst.edges[:, 0]] * s[:, inst.edges[:, 1]]) @ inst.J + s @ inst.h
+    w = np.exp(-beta * (E - E.min()))
+    w /= w.sum()
+    m1 = w @ s[:, spins]
+    ee = inst.edges[edges]
+    m2 = w @ (s[:, ee[:, 0]] * s[:, ee[:, 1]])
+    return m1, m2
+
+
+def _spins_of_cells(inst, X, cells):
+    from oracle.potts import Potts
+    P = Potts(inst)
+    out = {}
+    for n in cells:
+        for b, i in enumerate(P.spins[n]):
+            out[int(i)] = 1 if (X[n] >> b) & 1 else -1
+    return out
+
+
+def test_row_moments_first_row_match_brute_force():
+    # exact environment: the row moments of the empty configuration are the
+    # unconditioned <s_i>, <s_i s_j> of row 0
+    inst = make_instance("king", 81, jdist="uniform", hdist="uniform0.1", R=2, C=2, a=2)
+    beta = 0.9
+    env = contract_env(inst, beta, Options(chi=64, cut=1e-13))
+    net = env.net
+    X = np.zeros((1, 4), dtype=np.int64)
+    m1, m2, sp, ed = row_moments(net, env, 0, 0, X, np.ones((1, 1)))
+    assert len(ed) > 0
+    b1, b2 = _cond_brute(inst, beta, {}, sp, ed)
+    assert np.allclose(m1[0], b1, atol=1e-12)
+    assert np.allclose(m2[0], b2, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,kw,r,c", [("king", dict(R=2, C=3, a=2), 1, 1),
+                                         ("king", dict(R=3, C=3, a=1), 1, 2),
+                                         ("zephyr", dict(m=1, t=2), 1, 0)])
+def test_row_moments_mid_row_match_conditional_brute_force(kind, kw, r, c):
+    inst = make_instance(kind, 82, jdist="uniform", hdist="uniform0.1", **kw)
+    beta = 1.1
+    env = contract_env(inst, beta, Options(chi=64, cut=1e-13))
+    net = env.net
+    ncell = net.R * net.C
+    rng = np.random.default_rng(5)
+    X = np.zeros((2, ncell), dtype=np.int64)
+    n0 = r * net.C + c
+    for k in range(n0):
+        X[:, k] = rng.integers(0, 1 << int(net.P.k[k]), size=2)
+    # left vectors from the oracle's own marginals
+    Rr = right_envs(net, env, r, X)
+    L = np.ones((2, 1))
+    for cc in range(c):
+        _, vec = marginals(net, env, r, cc, X, L, Rr[cc])
+        L = vec[np.arange(2), X[:, r * net.C + cc]]
+    m1, m2, sp, ed = row_moments(net, env, r, c, X, L)
+    for b in range(2):
+        fixed = _spins_of_cells(inst, X[b], range(n0))
+        b1, b2 = _cond_brute(inst, beta, fixed, sp, ed)
+        assert np.allclose(m1[b], b1, atol=1e-11)
+        assert np.allclose(m2[b], b2, atol=1e-11)
+
+
+def test_row_moments_are_log_z_derivatives_of_the_approximate_network():
+    # for any fixed Psi_{r+1} (here a truncated one) the moments are
+    # -1/beta d log Z_b / d h_i and -1/beta d log Z_b / d J_ij
+    inst = make_instance("king", 83, jdist="uniform", hdist="uniform0.1", R=3, C=3, a=2)
+    beta, r, c, eps = 1.3, 1, 1, 1e-6
+    env = contract_env(inst, beta, Options(chi=3))
+    net = env.net
+    X = np.zeros((1, 9), dtype=np.int64)
+    X[0, :4] = [5, 9, 12, 3]
+    Rr = right_envs(net, env, r, X)
+    _, vec = marginals(net, env, r, 0, X, np.ones((1, 1)), Rr[0])
+    L = vec[:, X[0, 3]]
+    m1, m2, sp, ed = row_moments(net, env, r, c, X, L)
+    import copy
+
+    def lz(dh=None, dJ=None):
+        k = copy.deepcopy(inst)
+        if dh is not None:
+            k.h = k.h + dh
+        if dJ is not None:
+            k.J = k.J + dJ
+        return row_logz(_Net(k, beta), env, r, c, X[0], L[0])
+
+    for col in (0, 3, len(sp) - 1):
+        dh = np.zeros(inst.n_spins)
+        dh[sp[col]] = eps
+        fd = (lz(dh=dh) - lz(dh=-dh)) / (2 * eps)
+        assert abs(fd + beta * m1[0, col]) < 1e-7
+    for col in (0, len(ed) - 1):
+        dJ = np.zeros(len(inst.J))
+        dJ[ed[col]] = eps
+        fd = (lz(dJ=dJ) - lz(dJ=-dJ)) / (2 * eps)
+        assert abs(fd + beta * m2[0, col]) < 1e-7
+
+
+def test_row_moments_fixed_cluster_layout():
+    inst = make_instance("zephyr", 84, jdist="uniform", m=1, t=2)
+    net = _Net(inst, 1.0)
+    sp, ed = row_spins_edges(net, 1, 0)
+    cells = inst.cell_of[sp]
+    assert np.all(np.diff(cells) >= 0) and np.all(cells // net.C == 1)
+    assert np.all(inst.cell_of[inst.edges[ed, 0]] == inst.cell_of[inst.edges[ed, 1]])
