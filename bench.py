@@ -100,6 +100,37 @@ def cpu_baseline(inst, wl, counts, marg_per_step, power):
                 kind="oracle", sample=sample, seconds_per_step_extrapolated=t_step)
 
 
+def adjoint_compare(pk, torch, env, wl, inst):
+    """All row moments of one beam state (the start of row 1, where the beam is
+    full) by the adjoint sweep and by one clamped contraction per branch; both
+    include the forward right environments of the row."""
+    import numpy as np
+    beam = pk.Beam(env, wl["M"])
+    for _ in range(inst.C):
+        beam.step()
+    _, npar, _ = beam.info()
+    sp, ed = beam.row_layout()
+    beam.row_moments()  # layout upload and buffers
+    torch.cuda.synchronize()
+    t_adj = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        m1, m2 = beam.row_moments()
+        torch.cuda.synchronize()
+        t_adj.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    pb = beam.row_moments_per_branch()
+    torch.cuda.synchronize()
+    t_pb = time.perf_counter() - t0
+    n = npar * len(sp)
+    ta = float(np.median(t_adj))
+    return {"state": "start of row 1 (beam full)", "parents": int(npar), "row_spins": int(len(sp)),
+            "row_couplings": int(len(ed)), "adjoint_ms": ta * 1e3, "per_branch_ms": t_pb * 1e3,
+            "adjoint_spin_marginals_per_s": n / ta, "per_branch_spin_marginals_per_s": n / t_pb,
+            "speedup": t_pb / ta, "pair_moments_per_s_adjoint": npar * len(ed) / ta,
+            "max_abs_diff_adjoint_vs_per_branch": float((m1 - pb).abs().max().item())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -151,6 +182,8 @@ def main():
     counts = {"site": (prof.get("site_apply", (0, 0))[1] + prof.get("site_applyT", (0, 0))[1]) / args.steps,
               "med": (prof.get("med_apply", (0, 0))[1] + prof.get("med_applyT", (0, 0))[1]
                       + prof.get("medf_Y2", (0, 0))[1] + prof.get("medf_W2", (0, 0))[1]) / args.steps}
+    adj = adjoint_compare(pk, torch, res["env"], wl, inst)
+    print("adjoint comparison done", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, wl, counts, marg, args.power_iters)
@@ -165,7 +198,7 @@ def main():
                    "power_iters": args.power_iters},
         "best_energy": float(res["energies"][0]), "energy_gap_vs_oracle": None,
         "logZ": res["logZ"], "spin_marginals_per_step": marg,
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "adjoint": adj,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
     }
     print(json.dumps(out), flush=True)

@@ -152,6 +152,40 @@ tnb_status tnb_branch_step(tnb_beam* beam, double* p_disc_log, tnb_stream stream
 tnb_status tnb_beam_export(const tnb_beam* beam, int32_t K, int8_t* d_states, double* d_logp,
                            int32_t* count, tnb_stream stream);
 
+/* Layout of the row moments at the current step n = (r, c): the spins of
+ * the unfixed clusters (r, c) .. (r, cols-1), cluster by cluster in
+ * ascending spin index, and the couplings with both ends in one of those
+ * clusters, in edge order.  *n_spins and *n_edges (host, may be NULL)
+ * receive the counts; spins and edges (host, may be NULL) receive up to cap
+ * ids each (spin indices, edge indices into the instance).
+ * TNB_EINVAL when every cluster is already fixed. */
+tnb_status tnb_row_layout(const tnb_beam* beam, int32_t* n_spins, int32_t* n_edges, int32_t* spins,
+                          int32_t* edges, int32_t cap);
+
+/* Row moments by the adjoint of the row contraction (Eq. 9-10, Fig. 6b):
+ * for every parent b of the current step, <s_i>_b = -1/beta dlogZ_b/dh_i for
+ * every spin of tnb_row_layout and <s_i s_j>_b = -1/beta dlogZ_b/dJ_ij for
+ * every listed coupling, where Z_b is the network of Fig. 6(b) conditioned
+ * on b with the boundary MPS below row r held fixed.  One backward sweep
+ * over the row, left to right, reusing the right environments of the
+ * forward pass as checkpoints.  The values are signed ratios of the
+ * approximate contraction (no clipping), so they are exact derivatives of
+ * log|Z_b| and may leave [-1, 1] where the approximate environment has
+ * negative terms.  d_m1 (device) receives [n_parents][n_spins], d_m2
+ * (device, may be NULL) [n_parents][n_edges]; m1_len and m2_len are their
+ * capacities in doubles.
+ * Errors: TNB_EINVAL (sizes, finished beam), TNB_ENUMERIC (a zero or
+ * non-finite Z_b). */
+tnb_status tnb_row_moments(tnb_beam* beam, double* d_m1, int64_t m1_len, double* d_m2, int64_t m2_len,
+                           tnb_stream stream);
+
+/* The same <s_i>_b by the plain method, one contraction per branch: for
+ * every listed spin, Z_b(s_i = +1) and Z_b(s_i = -1) from two clamped
+ * contractions, each starting from the stored right environment of the
+ * spin's column; <s_i>_b = (Z+ - Z-) / (Z+ + Z-).  Same layout, errors and
+ * capacity rule as tnb_row_moments (no couplings). */
+tnb_status tnb_row_moments_per_branch(tnb_beam* beam, double* d_m1, int64_t m1_len, tnb_stream stream);
+
 /* Measurement support.  tnb_profile_enable(1) clears and starts recording a
  * pair of HIP events around every launch of the instrumented kernels, on the
  * stream the kernel runs on, together with its algorithmic flop and byte

@@ -169,6 +169,38 @@ class Beam(_Handle):
         _check(L.lib().tnb_branch_step(self._h, ctypes.byref(pd), _stream()))
         return pd.value
 
+    def row_layout(self):
+        """(spins, edges) of the row moments at the current step (numpy int32)."""
+        ns, ne = ctypes.c_int32(), ctypes.c_int32()
+        _check(L.lib().tnb_row_layout(self._h, ctypes.byref(ns), ctypes.byref(ne), None, None, 0))
+        cap = max(ns.value, ne.value, 1)
+        sp = np.zeros(cap, dtype=np.int32)
+        ed = np.zeros(cap, dtype=np.int32)
+        _check(L.lib().tnb_row_layout(self._h, ctypes.byref(ns), ctypes.byref(ne),
+                                      sp.ctypes.data_as(ctypes.c_void_p), ed.ctypes.data_as(ctypes.c_void_p), cap))
+        return sp[:ns.value], ed[:ne.value]
+
+    def row_moments(self, edges=True):
+        """Adjoint row moments: (m1 [parents, spins], m2 [parents, edges] or None)."""
+        import torch
+        _, npar, _ = self.info()
+        sp, ed = self.row_layout()
+        m1 = torch.empty((npar, len(sp)), dtype=torch.float64, device="cuda")
+        m2 = torch.empty((npar, len(ed)), dtype=torch.float64, device="cuda") if edges else None
+        _check(L.lib().tnb_row_moments(self._h, ctypes.c_void_p(m1.data_ptr()), m1.numel(),
+                                       ctypes.c_void_p(m2.data_ptr()) if m2 is not None else None,
+                                       m2.numel() if m2 is not None else 0, _stream()))
+        return m1, m2
+
+    def row_moments_per_branch(self):
+        """<s_i>_b of the same layout by one clamped contraction per branch."""
+        import torch
+        _, npar, _ = self.info()
+        sp, _ = self.row_layout()
+        m1 = torch.empty((npar, len(sp)), dtype=torch.float64, device="cuda")
+        _check(L.lib().tnb_row_moments_per_branch(self._h, ctypes.c_void_p(m1.data_ptr()), m1.numel(), _stream()))
+        return m1
+
     def export(self, K, n_spins):
         import torch
         st = torch.empty((K, n_spins), dtype=torch.int8, device="cuda")

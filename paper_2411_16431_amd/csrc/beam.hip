@@ -7,8 +7,8 @@
 // to left in four factorised passes:
 //   u[b][x][g]        = A_{2c}[v'(x)] R^{(c)}[:, pi_c(x)]
 //   U[b][xh][b'][g]   = sum_{x in (xh, b')} w(x) phi_b(x) u[b][x][g]
-//   V[b][a'][xh][be]  = sum_{b', g} A_{2c-1}[a' + da' b'][be][g] U[b][xh][b'][g]
-//   R^{(c-1)}[b][be][pi] = sum_xh W_h(h(pi), xh) V[b][a'(pi)][xh][be]
+//   V[b][xh][a'][be]  = sum_{b', g} U[b][xh][b'][g] A_{2c-1}[a' + da' b'][be][g]   (MFMA GEMM)
+//   R^{(c-1)}[b][be][pi] = sum_xh W_h(h(pi), xh) V[b][xh][a'(pi)][be]
 // The marginal of (r, c) is then q_b[x] = w phi_b W_h(x_{c-1}^b, x)
 // (L_b A_{2c-1}[..] A_{2c}[v'(x)]) . R_b^{(c)}[:, pi_c(x)].
 // Candidates are reduced exactly: within a parent, x values that agree on the
@@ -20,16 +20,10 @@
 #include <cstdlib>
 #include <memory>
 
-#include "env.h"
+#include "beam.h"
 
 namespace tnb {
 
-struct Cand {
-  uint64_t gkey;
-  uint64_t skey;  // ascending skey = descending score
-  uint32_t b;
-  uint32_t x;
-};
 
 __host__ __device__ inline uint64_t score_key(double v) {
   uint64_t u;
@@ -66,7 +60,6 @@ __global__ void bitonic_step(Cand* __restrict__ a, int64_t n, int64_t j, int64_t
   }
 }
 
-static unsigned nblk(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
 static void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st) {
   int lg = 0;
@@ -78,35 +71,6 @@ static void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st) {
   HIPC(hipGetLastError());
 }
 
-// ---- per-column geometry of the beam's row ----------------------------------
-struct UpNb {
-  uint32_t Bup_in_up = 0;  // spins of the upper cell facing n
-  uint32_t Bn = 0;         // spins of n facing the upper cell
-  int cell = -1;
-  const double* W = nullptr;
-  int64_t sp = 0, sq = 0;
-};
-struct BCol {
-  int n, k;
-  uint32_t PRR = 0, Bvd = 0, Bbd = 0, Bxh = 0;
-  int dpi = 1, dvd = 1, dbd = 1, dxh = 1, da2 = 1;  // da2: Psi site 2c-1 a' size
-  uint32_t pos_h = 0, pos_a = 0;                     // within PRR_{c-1}
-  uint32_t Bleft_h = 0;                              // spins of (r,c-1) facing n
-  const double* Wh = nullptr;                        // W(left, n)
-  int64_t Wh_sp = 0, Wh_sq = 0;
-  const double* w = nullptr;
-  UpNb up[3];
-  int nup = 0;
-};
-
-__device__ inline double phi_of(const BCol& c, const int32_t* __restrict__ Xb, uint32_t x) {
-  double f = 1.0;
-  for (int i = 0; i < c.nup; ++i) {
-    const UpNb& u = c.up[i];
-    f *= u.W[pext_dev(uint32_t(Xb[u.cell]), u.Bup_in_up) * u.sp + pext_dev(x, u.Bn) * u.sq];
-  }
-  return f;
-}
 
 // u[b][x][g] = sum_d A2c[vd(x)][g][d] * R[b][d][pi(x)]
 __global__ void renv_u_kernel(BCol c, const double* __restrict__ A2c, int Dl, int Dr,
@@ -146,32 +110,13 @@ __global__ void renv_U_kernel(BCol c, const int32_t* __restrict__ X, int ncell, 
     const int64_t d = int64_t(1) << c.k;
     for (int f = 0; f < nf; ++f) {
       const uint32_t x = base | pdep_dev(uint32_t(f), FREE);
-      acc = fma(c.w[x] * phi_of(c, Xb, x), u[(size_t(b) * d + x) * Dl + g], acc);
+      acc = fma(wloc(c, x) * phi_of(c, Xb, x), u[(size_t(b) * d + x) * Dl + g], acc);
     }
   }
   U[idx] = acc;
 }
 
-// V[b][a2][xh][be] = sum_{bd, g} A[a2 + da2*bd][be][g] U[b][xh][bd][g]
-__global__ void renv_V_kernel(BCol c, const double* __restrict__ A, int Dl, int Dr,
-                              const double* __restrict__ U, int nb, double* __restrict__ V) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t per = int64_t(c.da2) * c.dxh * Dl;
-  if (idx >= nb * per) return;
-  const int b = int(idx / per);
-  const int a2 = int((idx / (int64_t(c.dxh) * Dl)) % c.da2);
-  const int xh = int((idx / Dl) % c.dxh);
-  const int be = int(idx % Dl);
-  double acc = 0.0;
-  for (int bd = 0; bd < c.dbd; ++bd) {
-    const double* Ar = A + (size_t(a2 + c.da2 * bd) * Dl + be) * Dr;
-    const double* Ur = U + ((size_t(b) * c.dxh + xh) * c.dbd + bd) * Dr;
-    for (int g = 0; g < Dr; ++g) acc = fma(Ar[g], Ur[g], acc);
-  }
-  V[idx] = acc;
-}
-
-// R[b][be][pi] = sum_xh Wh(h(pi), xh) V[b][a(pi)][xh][be]   (pi over PRR_{c-1})
+// R[b][be][pi] = sum_xh Wh(h(pi), xh) V[b][xh][a(pi)][be]   (pi over PRR_{c-1})
 __global__ void renv_R_kernel(BCol c, int dpi_prev, const double* __restrict__ V, int nb, int Dl,
                               double* __restrict__ R) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -183,11 +128,11 @@ __global__ void renv_R_kernel(BCol c, int dpi_prev, const double* __restrict__ V
   const uint32_t h = pext_dev(pi, c.pos_h), a2 = pext_dev(pi, c.pos_a);
   double acc = 0.0;
   for (int xh = 0; xh < c.dxh; ++xh)
-    acc = fma(c.Wh[h * c.Wh_sp + xh * c.Wh_sq], V[((size_t(b) * c.da2 + a2) * c.dxh + xh) * Dl + be], acc);
+    acc = fma(c.Wh[h * c.Wh_sp + xh * c.Wh_sq], V[((size_t(b) * c.dxh + xh) * c.da2 + a2) * Dl + be], acc);
   R[idx] = acc;
 }
 
-__global__ void normalise_rows_kernel(double* __restrict__ R, int64_t per, int nb) {
+__global__ void normalise_rows_kernel(double* __restrict__ R, int64_t per, int nb, double* __restrict__ logs) {
   __shared__ double red[256];
   const int b = blockIdx.x;
   double m = 0.0;
@@ -200,6 +145,7 @@ __global__ void normalise_rows_kernel(double* __restrict__ R, int64_t per, int n
   }
   const double s = red[0] > 0.0 ? 1.0 / red[0] : 1.0;
   for (int64_t i = threadIdx.x; i < per; i += blockDim.x) R[b * per + i] *= s;
+  if (logs && threadIdx.x == 0 && red[0] > 0.0) logs[b] += log(red[0]);
 }
 
 // T[b][bd][m] = sum_a L[b][a] A[afix(b) + da2*bd][a][m]
@@ -230,7 +176,7 @@ __global__ void beam_q_kernel(BCol c, int has_left, int left_cell, const int32_t
   const int b = int(idx / d);
   const uint32_t x = uint32_t(idx % d);
   const int32_t* Xb = X + size_t(b) * ncell;
-  double g = c.w[x] * phi_of(c, Xb, x);
+  double g = wloc(c, x) * phi_of(c, Xb, x);
   if (has_left)
     g *= c.Wh[pext_dev(uint32_t(Xb[left_cell]), c.Bleft_h) * c.Wh_sp + pext_dev(x, c.Bxh) * c.Wh_sq];
   const double* Tb = T + (size_t(b) * c.dbd + pext_dev(x, c.Bbd)) * Dl;
@@ -455,32 +401,12 @@ __global__ void fill_i(int32_t* __restrict__ x, int64_t n, int32_t v, int iota) 
 
 using namespace tnb;
 
-struct tnb_beam {
-  uint32_t kind = KIND_BEAM;
-  tnb_env* env = nullptr;
-  int M = 0, step = 0, npar = 1, ncell = 0;
-  DevBuf<int32_t> X, Xn, rid, ridn;
-  DevBuf<double> logp, logpn, L, Ln;
-  int Ld = 1;
-  std::vector<DevBuf<double>> R;  // R[c]: [anc][Dr(2c)][dpi_c]
-  int nanc = 0;
-  double pd_log = -INFINITY;
-  DevBuf<double> q, score, T, u, U, V;
-  DevBuf<Cand> cand, win;
-  DevBuf<int> flag, dead;
-  DevBuf<int64_t> pos, total;
-  DevBuf<uint32_t> words, cls, km;
-  DevBuf<int> kc;
-  DevBuf<int32_t> cell_of, bit;
-  std::vector<BCol> geo;  // of the current row
-  int geo_row = -1;
-};
 
 namespace tnb {
 
-static void ensure(DevBuf<double>& b, size_t n) { if (b.n < n) b.alloc(n + n / 4 + 16); }
+void ensure(DevBuf<double>& b, size_t n) { if (b.n < n) b.alloc(n + n / 4 + 16); }
 
-static std::vector<BCol> beam_geom(const tnb_clusters* cl, int r) {
+std::vector<BCol> beam_geom(const tnb_clusters* cl, int r) {
   const Lattice& L = cl->lat;
   std::vector<BCol> g(L.C);
   const double* ones = unit_weight();
@@ -522,8 +448,54 @@ static std::vector<BCol> beam_geom(const tnb_clusters* cl, int r) {
   return g;
 }
 
+void row_step(tnb_beam* bm, const BCol& cc, int c, int nb, const double* Rin, double* Rout, double* logs,
+              hipStream_t st) {
+  const int r = bm->geo_row;
+  const Mps& psi = bm->env->psi[r + 1];
+  const Site& A2c = psi.sites[2 * c];
+  const Site& A2m = psi.sites[2 * c - 1];
+  const int64_t d = int64_t(1) << cc.k;
+  ensure(bm->u, size_t(nb) * d * A2c.dl);
+  {
+  KTimer _tu("renv_u", st, 2.0 * nb * double(d) * A2c.dl * A2c.dr, 8.0 * (double(nb) * d * A2c.dl + A2c.size()));
+  hipLaunchKernelGGL(renv_u_kernel, dim3(nblk(int64_t(nb) * d * A2c.dl)), dim3(256), 0, st, cc, A2c.data.p,
+                     A2c.dl, A2c.dr, Rin, nb, bm->u.p);
+  }
+  ensure(bm->U, size_t(nb) * cc.dxh * cc.dbd * A2c.dl);
+  {
+  KTimer _tU("renv_U", st, 2.0 * nb * double(d) * A2c.dl, 8.0 * (double(nb) * d * A2c.dl));
+  hipLaunchKernelGGL(renv_U_kernel, dim3(nblk(int64_t(nb) * cc.dxh * cc.dbd * A2c.dl)), dim3(256), 0, st, cc,
+                     bm->X.p, bm->ncell, bm->u.p, nb, A2c.dl, bm->U.p);
+  }
+  ensure(bm->V, size_t(nb) * cc.da2 * cc.dxh * A2m.dl);
+  {
+    // V[b][xh][a2][be] = sum_{bd, g} U[b][xh][bd][g] A[a2 + da2 bd][be][g]: rows (b, xh),
+    // columns (a2, be), reduction (bd, g) -- one GEMM on the matrix cores
+    const int Dl = A2m.dl, Dr = A2m.dr;
+    la::Operand Uop{bm->U.p, 0, la::Ix{0, 0, int64_t(cc.dbd) * Dr}, la::Ix{0, 0, 1}};
+    la::Operand Aop{A2m.data.p, 0, la::Ix{uint32_t(Dr), int64_t(cc.da2) * Dl * Dr, 1}, la::Ix{0, 0, Dr}};
+    const int N = cc.da2 * Dl;
+    la::gemm_mfma(1, nb * cc.dxh, N, cc.dbd * Dr, Uop, Aop, bm->V.p, la::Ix{0, 0, N}, la::Ix{0, 0, 1}, 0, 1.0, 0.0,
+                  st, "renv_V");
+  }
+  const int dpi_prev = bm->geo[c - 1].dpi;
+  {
+  KTimer _tR("renv_R", st, 2.0 * nb * double(A2m.dl) * dpi_prev * cc.dxh,
+             8.0 * (double(nb) * cc.da2 * cc.dxh * A2m.dl + double(nb) * A2m.dl * dpi_prev));
+  hipLaunchKernelGGL(renv_R_kernel, dim3(nblk(int64_t(nb) * A2m.dl * dpi_prev)), dim3(256), 0, st, cc, dpi_prev,
+                     bm->V.p, nb, A2m.dl, Rout);
+  }
+  hipLaunchKernelGGL(normalise_rows_kernel, dim3(nb), dim3(256), 0, st, Rout, int64_t(A2m.dl) * dpi_prev, nb, logs);
+  HIPC(hipGetLastError());
+}
+
+void normalise_rows(double* R, int64_t per, int nb, double* logs, hipStream_t st) {
+  hipLaunchKernelGGL(normalise_rows_kernel, dim3(nb), dim3(256), 0, st, R, per, nb, logs);
+  HIPC(hipGetLastError());
+}
+
 // right environments of every current parent for row r
-static void row_envs(tnb_beam* bm, int r, hipStream_t st) {
+void row_envs(tnb_beam* bm, int r, hipStream_t st) {
   const tnb_clusters* cl = bm->env->cl;
   const Lattice& L = cl->lat;
   const Mps& psi = bm->env->psi[r + 1];
@@ -539,40 +511,9 @@ static void row_envs(tnb_beam* bm, int r, hipStream_t st) {
     hipLaunchKernelGGL(fill_d, dim3(nblk(nb)), dim3(256), 0, st, Rl.p, int64_t(nb), 1.0);
   }
   for (int c = C - 1; c >= 1; --c) {
-    const BCol& cc = bm->geo[c];
-    const Site& A2c = psi.sites[2 * c];
     const Site& A2m = psi.sites[2 * c - 1];
-    const int64_t d = int64_t(1) << cc.k;
-    ensure(bm->u, size_t(nb) * d * A2c.dl);
-    {
-    KTimer _tu("renv_u", st, 2.0 * nb * double(d) * A2c.dl * A2c.dr, 8.0 * (double(nb) * d * A2c.dl + A2c.size()));
-    hipLaunchKernelGGL(renv_u_kernel, dim3(nblk(int64_t(nb) * d * A2c.dl)), dim3(256), 0, st, cc, A2c.data.p,
-                       A2c.dl, A2c.dr, bm->R[c].p, nb, bm->u.p);
-    }
-    ensure(bm->U, size_t(nb) * cc.dxh * cc.dbd * A2c.dl);
-    {
-    KTimer _tU("renv_U", st, 2.0 * nb * double(d) * A2c.dl, 8.0 * (double(nb) * d * A2c.dl));
-    hipLaunchKernelGGL(renv_U_kernel, dim3(nblk(int64_t(nb) * cc.dxh * cc.dbd * A2c.dl)), dim3(256), 0, st, cc,
-                       bm->X.p, bm->ncell, bm->u.p, nb, A2c.dl, bm->U.p);
-    }
-    ensure(bm->V, size_t(nb) * cc.da2 * cc.dxh * A2m.dl);
-    {
-    KTimer _tV("renv_V", st, 2.0 * nb * double(cc.da2) * cc.dxh * A2m.dl * cc.dbd * A2m.dr,
-               8.0 * (A2m.size() + double(nb) * cc.dxh * cc.dbd * A2c.dl + double(nb) * cc.da2 * cc.dxh * A2m.dl));
-    hipLaunchKernelGGL(renv_V_kernel, dim3(nblk(int64_t(nb) * cc.da2 * cc.dxh * A2m.dl)), dim3(256), 0, st, cc,
-                       A2m.data.p, A2m.dl, A2m.dr, bm->U.p, nb, bm->V.p);
-    }
-    const int dpi_prev = bm->geo[c - 1].dpi;
-    DevBuf<double>& Rn = bm->R[c - 1];
-    Rn.alloc(size_t(nb) * A2m.dl * dpi_prev);
-    {
-    KTimer _tR("renv_R", st, 2.0 * nb * double(A2m.dl) * dpi_prev * cc.dxh,
-               8.0 * (double(nb) * cc.da2 * cc.dxh * A2m.dl + double(nb) * A2m.dl * dpi_prev));
-    hipLaunchKernelGGL(renv_R_kernel, dim3(nblk(int64_t(nb) * A2m.dl * dpi_prev)), dim3(256), 0, st, cc, dpi_prev,
-                       bm->V.p, nb, A2m.dl, Rn.p);
-    }
-    hipLaunchKernelGGL(normalise_rows_kernel, dim3(nb), dim3(256), 0, st, Rn.p, int64_t(A2m.dl) * dpi_prev, nb);
-    HIPC(hipGetLastError());
+    bm->R[c - 1].alloc(size_t(nb) * A2m.dl * bm->geo[c - 1].dpi);
+    row_step(bm, bm->geo[c], c, nb, bm->R[c].p, bm->R[c - 1].p, nullptr, st);
   }
   hipLaunchKernelGGL(fill_i, dim3(nblk(nb)), dim3(256), 0, st, bm->rid.p, int64_t(nb), 0, 1);
   ensure(bm->L, size_t(bm->M) * 1);
@@ -581,7 +522,7 @@ static void row_envs(tnb_beam* bm, int r, hipStream_t st) {
 }
 
 // q[b][x] for the current step (row environments must be in place)
-static void compute_q(tnb_beam* bm, hipStream_t st) {
+void compute_q(tnb_beam* bm, hipStream_t st) {
   const tnb_clusters* cl = bm->env->cl;
   const Lattice& L = cl->lat;
   const int r = bm->step / L.C, c = bm->step % L.C;
@@ -593,22 +534,33 @@ static void compute_q(tnb_beam* bm, hipStream_t st) {
   const int64_t d = int64_t(1) << cc.k;
   // T[b][bd][m]
   ensure(bm->T, size_t(nb) * cc.dbd * A2c.dl);
-  int left = -1;
   if (c == 0) {
     hipLaunchKernelGGL(fill_d, dim3(nblk(nb)), dim3(256), 0, st, bm->T.p, int64_t(nb), 1.0);
   } else {
     const Site& A2m = psi.sites[2 * c - 1];
-    left = L.cell(r, c - 1);
+    const int left = L.cell(r, c - 1);
     uint32_t la = cl->B(left, L.cell(r + 1, c));
     hipLaunchKernelGGL(beam_T_kernel, dim3(nblk(int64_t(nb) * cc.dbd * A2m.dr)), dim3(256), 0, st, cc, la, left,
                        bm->X.p, bm->ncell, bm->L.p, bm->Ld, A2m.data.p, A2m.dl, A2m.dr, nb, bm->T.p);
   }
   ensure(bm->q, size_t(nb) * d);
+  q_against(bm, cc, bm->R[c].p, bm->rid.p, bm->q.p, st);
+}
+
+void q_against(tnb_beam* bm, const BCol& cc, const double* Rc, const int32_t* rid, double* q, hipStream_t st) {
+  const tnb_clusters* cl = bm->env->cl;
+  const Lattice& L = cl->lat;
+  const int r = bm->step / L.C, c = bm->step % L.C;
+  const Mps& psi = bm->env->psi[r + 1];
+  const Site& A2c = psi.sites[2 * c];
+  const int nb = bm->npar;
+  const int64_t d = int64_t(1) << cc.k;
+  const int left = c > 0 ? L.cell(r, c - 1) : 0;
   {
   KTimer _tq("beam_q", st, double(nb) * d * (2.0 * A2c.dl * A2c.dr + 2.0 * A2c.dr),
              8.0 * (double(nb) * d + A2c.size() + double(bm->nanc) * A2c.dr * cc.dpi + double(nb) * cc.dbd * A2c.dl));
-  hipLaunchKernelGGL(beam_q_kernel, dim3(nblk(int64_t(nb) * d)), dim3(256), 0, st, cc, c > 0 ? 1 : 0, left < 0 ? 0 : left,
-                     bm->X.p, bm->ncell, bm->T.p, A2c.data.p, A2c.dl, A2c.dr, bm->R[c].p, bm->rid.p, nb, bm->q.p);
+  hipLaunchKernelGGL(beam_q_kernel, dim3(nblk(int64_t(nb) * d)), dim3(256), 0, st, cc, c > 0 ? 1 : 0, left,
+                     bm->X.p, bm->ncell, bm->T.p, A2c.data.p, A2c.dl, A2c.dr, Rc, rid, nb, q);
   }
   HIPC(hipGetLastError());
 }

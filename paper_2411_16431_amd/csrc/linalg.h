@@ -49,3 +49,28 @@ void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double*
 
 }  // namespace la
 }  // namespace tnb
+
+namespace tnb {
+namespace la {
+
+// Index map of one operand dimension: i -> (i / n0) * s1 + (i % n0) * s0, or
+// i * s0 when n0 == 0.  It lets a GEMM read tensors whose row or column
+// index is a pair of tensor indices with unrelated strides.
+struct Ix {
+  uint32_t n0 = 0;
+  int64_t s1 = 0, s0 = 0;
+};
+struct Operand {
+  const double* p = nullptr;
+  int64_t bs = 0;  // batch stride
+  Ix r, c;         // row and column maps
+};
+
+// C(m, n) = alpha * sum_k A(m, k) B(k, n) + beta * C(m, n) for every batch,
+// on the FP64 matrix cores (16x16x4 MFMA), 128 x 64 output tiles, each tile
+// owned by one workgroup and summed over all of K in order (deterministic).
+void gemm_mfma(int batch, int M, int N, int K, const Operand& A, const Operand& B, double* C, Ix cr, Ix cc,
+               int64_t cbs, double alpha, double beta, hipStream_t s, const char* timer = "gemm_mfma");
+
+}  // namespace la
+}  // namespace tnb

@@ -447,3 +447,177 @@ void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double*
 
 }  // namespace la
 }  // namespace tnb
+
+// ---------------------------------------------------------------------------
+// FP64 GEMM on the matrix cores.  v_mfma_f64_16x16x4f64 multiplies a 16x4 A
+// block by a 4x16 B block: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[4 v + l / 16][l % 16] in item v.
+// A workgroup of four waves owns a 128 x 64 tile of C; each wave a 64 x 32
+// sub-tile (4 x 2 MFMA blocks).  K advances in slices of 16 staged in LDS,
+// the next slice prefetched into registers while the current one is used.
+namespace tnb {
+namespace la {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int GM = 128, GN = 64, GK = 16;
+
+__device__ __forceinline__ int64_t ix_off(uint32_t i, const Ix& x) {
+  return x.n0 ? int64_t(i / x.n0) * x.s1 + int64_t(i % x.n0) * x.s0 : int64_t(i) * x.s0;
+}
+
+__global__ void __launch_bounds__(256) gemm_mfma_kernel(int M, int N, int K, Operand A, Operand B, double* __restrict__ C,
+                                                        Ix cr, Ix cc, int64_t cbs, double alpha, double beta,
+                                                        int a_kfast, int b_kfast, int tiles_n) {
+  __shared__ double As[GK][GM + 1];
+  __shared__ double Bs[GK][GN + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int tm0 = int(blockIdx.x / tiles_n) * GM, tn0 = int(blockIdx.x % tiles_n) * GN;
+  const int b = blockIdx.y;
+  const double* Ap = A.p + b * A.bs;
+  const double* Bp = B.p + b * B.bs;
+  // Staging: 8 A and 4 B elements per thread.  Along the unit-stride index
+  // consecutive threads take consecutive elements; the other index of a
+  // thread's elements is fixed, so its offsets are computed once.
+  double ra[8], rb[4];
+  // A: kfast -> k = t % 16 fixed, m = t / 16 + 16 i;  else m = t % 128 fixed, k = t / 128 + 2 i
+  int64_t a_fixed[8];
+  int a_ok = 0;
+  if (a_kfast) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int gm = tm0 + t / GK + 16 * i;
+      a_fixed[i] = gm < M ? ix_off(uint32_t(gm), A.r) : 0;
+      a_ok |= (gm < M) << i;
+    }
+  } else {
+    const int gm = tm0 + t % GM;
+    a_fixed[0] = gm < M ? ix_off(uint32_t(gm), A.r) : 0;
+    a_ok = gm < M ? 0xff : 0;
+  }
+  // B: kfast -> k = t % 16 fixed, n = t / 16 + 16 i;  else n = t % 64 fixed, k = t / 64 + 4 i
+  int64_t b_fixed[4];
+  int b_ok = 0;
+  if (b_kfast) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gn = tn0 + t / GK + 16 * i;
+      b_fixed[i] = gn < N ? ix_off(uint32_t(gn), B.c) : 0;
+      b_ok |= (gn < N) << i;
+    }
+  } else {
+    const int gn = tn0 + t % GN;
+    b_fixed[0] = gn < N ? ix_off(uint32_t(gn), B.c) : 0;
+    b_ok = gn < N ? 0xf : 0;
+  }
+  auto load = [&](int k0) {
+    if (a_kfast) {
+      const int gk = k0 + t % GK;
+      const int64_t ko = gk < K ? ix_off(uint32_t(gk), A.c) : 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ra[i] = (gk < K && (a_ok >> i & 1)) ? Ap[a_fixed[i] + ko] : 0.0;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gk = k0 + t / GM + 2 * i;
+        ra[i] = (gk < K && a_ok) ? Ap[a_fixed[0] + ix_off(uint32_t(gk), A.c)] : 0.0;
+      }
+    }
+    if (b_kfast) {
+      const int gk = k0 + t % GK;
+      const int64_t ko = gk < K ? ix_off(uint32_t(gk), B.r) : 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rb[i] = (gk < K && (b_ok >> i & 1)) ? Bp[b_fixed[i] + ko] : 0.0;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gk = k0 + t / GN + 4 * i;
+        rb[i] = (gk < K && b_ok) ? Bp[b_fixed[0] + ix_off(uint32_t(gk), B.r)] : 0.0;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (a_kfast) As[t % GK][t / GK + 16 * i] = ra[i];
+      else As[t / GM + 2 * i][t % GM] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (b_kfast) Bs[t % GK][t / GK + 16 * i] = rb[i];
+      else Bs[t / GN + 4 * i][t % GN] = rb[i];
+    }
+  };
+  v4d acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int li = lane & 15, lk = lane >> 4;
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + GK < K) load(k0 + GK);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      double a[4], bv[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk + lk][wm * 64 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = Bs[kk + lk][wn * 32 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  double* Cb = C + b * cbs;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = tn0 + wn * 32 + j * 16 + li;
+      if (gn >= N) continue;
+      const int64_t on = ix_off(uint32_t(gn), cc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = tm0 + wm * 64 + i * 16 + 4 * v + lk;
+        if (gm >= M) continue;
+        double* dst = Cb + ix_off(uint32_t(gm), cr) + on;
+        const double r = alpha * acc[i][j][v];
+        *dst = beta == 0.0 ? r : r + beta * *dst;
+      }
+    }
+}
+
+static bool kfast(const Ix& k, const Ix& other) {
+  // stage along k when k is the unit-stride index of the operand
+  const int64_t sk = k.s0 < 0 ? -k.s0 : k.s0, so = other.s0 < 0 ? -other.s0 : other.s0;
+  return sk <= so;
+}
+
+void gemm_mfma(int batch, int M, int N, int K, const Operand& A, const Operand& B, double* C, Ix cr, Ix cc,
+               int64_t cbs, double alpha, double beta, hipStream_t s, const char* timer) {
+  if (batch <= 0 || M <= 0 || N <= 0) return;
+  const int tiles_m = (M + GM - 1) / GM, tiles_n = (N + GN - 1) / GN;
+  const int64_t tiles = int64_t(tiles_m) * tiles_n;
+  if (tiles > 0x7fffffff) fail(TNB_EUNSUPPORTED, "GEMM too large");
+  KTimer _t(timer, s, 2.0 * M * double(N) * double(K) * batch,
+            8.0 * (double(M) * K + double(K) * N + double(M) * N) * batch);
+  for (int b0 = 0; b0 < batch; b0 += 65535) {
+    const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    Operand a = A, bb = B;
+    a.p += A.bs * b0;
+    bb.p += B.bs * b0;
+    hipLaunchKernelGGL(gemm_mfma_kernel, dim3(unsigned(tiles), unsigned(nb)), dim3(256), 0, s, M, N, K, a, bb,
+                       C + cbs * b0, cr, cc, cbs, alpha, beta, kfast(A.c, A.r) ? 1 : 0, kfast(B.r, B.c) ? 1 : 0,
+                       tiles_n);
+  }
+  HIPC(hipGetLastError());
+}
+
+}  // namespace la
+}  // namespace tnb
