@@ -187,8 +187,9 @@ __global__ void site_applyT_kernel(int k, uint32_t Bup, uint32_t FREE, int nfree
 //            out[rho]         = sum_b' A[a'(rho) + da' b'] Y2[rd(rho)][b'][hR(rho)]
 //   applyT:  W2[rd][b'][hL]   = sum_{rho: rd(rho)=rd} Wh(h(rho), h'(b',hL)) A[a'(rho)+da'b']^T Y[rho]
 //            G2[ld][rd]       = sum_{l: l_d(l)=ld} K[l]^T W2[rd][b'(l)][hL(l)]
-// Bins (hR or hL values) are spread over the grid in chunks of 16 held in
-// registers.  Every output block is owned by one workgroup: no atomics.
+// Bins (hR or hL values) are spread over the grid in chunks of 16, the M
+// dimension of the second-stage MFMA.  Every output block is owned by one
+// workgroup: no atomics.
 struct MedF {
   RowGeom::Med md;
   uint32_t hR_pos = 0;   // horizontal bits of rho outside rho_d (positions within rho)
@@ -197,205 +198,432 @@ struct MedF {
   int chR = 1, chL = 1;  // chunks of 16 bins
 };
 
-template <int PT>
-__global__ void __launch_bounds__(256) medf_Y2_kernel(MedF f, const double* __restrict__ Kc, int Db, int Dg,
-                                                      const double* __restrict__ X2, int s,
-                                                      double* __restrict__ Y2) {
+// ---- the factored mediating diagram on the matrix cores -------------------
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and holds D[4 v + l / 16][l % 16] in item v of the result.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Binned two-stage contraction (medf_Y2 and medf_W2).  For the items t of the
+// block's class:
+//   T_t = P_t (16 rows of b x Kd) . Q_t (Kd x s)          stage 1, one wave per item
+//   Out[h][b][j] += sum_t w_t[h] T_t[b][j]                stage 2, a GEMM over t
+// MODE 0 (apply):  t = l with b'(l) = b2, P_t = K[l], Q_t = X2[l_d(l)][rd],
+//                  w_t[h] = Wh(h(rho_d = rd, hR = 16 chunk + h), h'(l))
+// MODE 1 (applyT): t = rho with rho_d(rho) = rd, P_t = A[a'(rho) + da' b2]^T,
+//                  Q_t = Y[rho], w_t[h] = Wh(h(rho), h'(b2, hL = 16 chunk + h))
+// Four items per round: each wave stages its item's tiles in LDS and forms T_t;
+// the four T_t go through LDS into the B layout of stage 2, where wave w owns
+// rows b = 4w .. 4w+3 of the block's 16-row b tile.
+template <int MODE, int NJ>
+__global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __restrict__ P,
+                                                     const double* __restrict__ Q, int Da, int Db, int Kd, int s,
+                                                     double* __restrict__ out) {
   extern __shared__ double sh[];
-  double* Ks = sh;              // Db x Dg
-  double* Xs = sh + Db * Dg;    // Dg x s
-  double* wsh = Xs + Dg * s;    // 16 horizontal weights
+  // P rows are padded to a power of two (lgK) so the staging index splits
+  // with a shift; the MFMA loop still stops at Kp
+  const int Kp = (Kd + 3) & ~3, lgK = 32 - __clz(Kp - 1), PS = (1 << lgK) + 1, QS = 16 * NJ;
+  double* Ps = sh;                  // [4][16][PS]
+  double* Qs = Ps + 4 * 16 * PS;    // [4][Kp][QS]
+  double* Ts = Qs + 4 * Kp * QS;    // [4][16][QS]
+  double* Ws = Ts + 4 * 16 * QS;    // [4][16]
   const RowGeom::Med& md = f.md;
-  const uint32_t chunk = blockIdx.x % f.chR;
-  const uint32_t pair = blockIdx.x / f.chR;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nch = MODE == 0 ? f.chR : f.chL, nH = MODE == 0 ? f.nHR : f.nHL;
+  const uint32_t chunk = blockIdx.x % nch, pair = blockIdx.x / nch;
   const uint32_t rd = pair / md.db2, b2 = pair % md.db2;
-  const uint32_t rho_d_bits = pdep_dev(rd, md.pos_d_rho);
-  const int nb = min(16, f.nHR - int(chunk) * 16);
-  double acc[16][PT];
+  const int b0 = blockIdx.y * 16;
+  const int nbins = min(16, nH - int(chunk) * 16);
+  const int nitems = MODE == 0 ? md.dL / md.db2 : md.dR / md.drd;
+  const uint32_t fixed_bits = MODE == 0 ? pdep_dev(b2, md.pos_b2) : pdep_dev(rd, md.pos_d_rho);
+  const uint32_t free_bits = MODE == 0 ? (uint32_t(md.dL - 1) & ~md.pos_b2) : (uint32_t(md.dR - 1) & ~md.pos_d_rho);
+  double* Pw = Ps + w * 16 * PS;
+  double* Qw = Qs + w * Kp * QS;
+  double* Tw = Ts + w * 16 * QS;
+  double* Ww = Ws + w * 16;
+  v4d acc[4][NJ];
 #pragma unroll
-  for (int h = 0; h < 16; ++h)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int p = 0; p < PT; ++p) acc[h][p] = 0.0;
-  const uint32_t freeL = uint32_t(md.dL - 1) & ~md.pos_b2;
-  const int nl = md.dL / md.db2;
-  for (int fl = 0; fl < nl; ++fl) {
-    const uint32_t l = pdep_dev(b2, md.pos_b2) | pdep_dev(uint32_t(fl), freeL);
-    const uint32_t ld = pext_dev(l, md.pos_d_ell);
-    const uint32_t hl = pext_dev(l, md.pos_h_ell);
-    __syncthreads();
-    for (int i = threadIdx.x; i < Db * Dg; i += blockDim.x) Ks[i] = Kc[size_t(l) * Db * Dg + i];
-    const double* Xg = X2 + (size_t(ld) * md.drd + rd) * Dg * s;
-    for (int i = threadIdx.x; i < Dg * s; i += blockDim.x) Xs[i] = Xg[i];
-    if (int(threadIdx.x) < nb) {
-      const uint32_t rho = rho_d_bits | pdep_dev(chunk * 16u + threadIdx.x, f.hR_pos);
-      wsh[threadIdx.x] = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + hl * md.Wh_sq];
+    for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int t0 = 0; t0 < nitems; t0 += 4) {
+    const int t = t0 + w;
+    __syncthreads();  // the previous round's stage 2 is done with Ts and Ws
+    v4d tt[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) tt[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (t < nitems) {
+      const uint32_t item = fixed_bits | pdep_dev(uint32_t(t), free_bits);
+      const double* Pt;
+      const double* Qt;
+      double wgt = 0.0;
+      if (MODE == 0) {
+        const uint32_t l = item;
+        Pt = P + size_t(l) * Db * Kd;  // K[l][b][g], Kd = Dg
+        Qt = Q + (size_t(pext_dev(l, md.pos_d_ell)) * md.drd + rd) * Kd * s;
+        if (li < nbins) {
+          const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(chunk * 16u + li, f.hR_pos);
+          wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+        }
+      } else {
+        const uint32_t rho = item;
+        Pt = P + size_t(pext_dev(rho, md.pos_a2) + md.da2 * b2) * Da * Db;  // A[sigma][a][b], Kd = Da
+        Qt = Q + size_t(rho) * Da * s;
+        if (li < nbins) {
+          const uint32_t l = pdep_dev(b2, md.pos_b2) | pdep_dev(chunk * 16u + li, f.hL_pos);
+          wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+        }
+      }
+      if (lane < 16) Ww[lane] = wgt;
+      // P tile: rows b0 .. b0+15 of b, columns k < Kp (zero padded)
+      for (int i = lane; i < (16 << lgK); i += 64) {
+        int r, k;
+        if (MODE == 0) { r = i >> lgK; k = i & ((1 << lgK) - 1); }
+        else { k = i >> 4; r = i & 15; }
+        const int b = b0 + r;
+        double v = 0.0;
+        if (b < Db && k < Kd) v = MODE == 0 ? Pt[size_t(b) * Kd + k] : Pt[size_t(k) * Db + b];
+        Pw[r * PS + k] = v;
+      }
+      for (int i = lane; i < Kp * QS; i += 64) {
+        const int k = i / QS, j = i % QS;
+        Qw[i] = (k < Kd && j < s) ? Qt[size_t(k) * s + j] : 0.0;
+      }
+    } else if (lane < 16) {
+      Ww[lane] = 0.0;
     }
+    __syncthreads();  // staged tiles visible
+    if (t < nitems) {
+#pragma unroll 2
+      for (int kk = 0; kk < Kp; kk += 4) {
+        const double a = Pw[li * PS + kk + lk];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) tt[j] = mfma16(a, Qw[(kk + lk) * QS + 16 * j + li], tt[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tw[(4 * v + lk) * QS + 16 * j + li] = tt[j][v];
     __syncthreads();
+    // stage 2: A[h][k] = w_k[h], B[k][(b, j)] = T_k[b][j]
+    const double a2 = Ws[lk * 16 + li];
 #pragma unroll
-    for (int p = 0; p < PT; ++p) {
-      const int idx = threadIdx.x + p * blockDim.x;
-      if (idx < Db * s) {
-        const int b = idx / s, j = idx % s;
-        double t = 0.0;
-        for (int g = 0; g < Dg; ++g) t = fma(Ks[b * Dg + g], Xs[g * s + j], t);
+    for (int bl = 0; bl < 4; ++bl) {
+      const int b = 4 * w + bl;
 #pragma unroll
-        for (int h = 0; h < 16; ++h)
-          if (h < nb) acc[h][p] = fma(wsh[h], t, acc[h][p]);
+      for (int j = 0; j < NJ; ++j) acc[bl][j] = mfma16(a2, Ts[lk * 16 * QS + b * QS + 16 * j + li], acc[bl][j]);
+    }
+  }
+  double* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
+#pragma unroll
+  for (int bl = 0; bl < 4; ++bl) {
+    const int b = b0 + 4 * w + bl;
+    if (b >= Db) continue;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int jj = 16 * j + li;
+      if (jj >= s) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int h = 4 * v + lk;
+        if (h < nbins) o[(size_t(h) * Db + b) * s + jj] = acc[bl][j][v];
       }
     }
   }
-  double* out = Y2 + (size_t(pair) * f.nHR + chunk * 16u) * Db * s;
-#pragma unroll
-  for (int p = 0; p < PT; ++p) {
-    const int idx = threadIdx.x + p * blockDim.x;
-    if (idx < Db * s)
-#pragma unroll
-      for (int h = 0; h < 16; ++h)
-        if (h < nb) out[size_t(h) * Db * s + idx] = acc[h][p];
-  }
 }
 
-// out[rho] (Da x s) = sum_b' A[a'(rho) + da' b'] Y2[rd(rho)][b'][hR(rho)]
-template <int PT>
-__global__ void __launch_bounds__(256) medf_out_kernel(MedF f, const double* __restrict__ A, int Da, int Db,
-                                                       const double* __restrict__ Y2, int s,
-                                                       double* __restrict__ out) {
-  extern __shared__ double sh[];
-  double* As = sh;             // Da x Db
-  double* Ys = sh + Da * Db;   // Db x s
+// Plain accumulation over a class (medf_G2 and medf_out):
+//   Out[blk] (rows x s) = sum_t P_t (rows x Db) . Q_t (Db x s)
+// MODE 0 (G2):  blk = (l_d, rho_d), t = l with l_d(l) = l_d, P_t = K[l]^T,
+//               Q_t = W2[rho_d][b'(l)][hL(l)]
+// MODE 1 (out): blk = rho, t = b', P_t = A[a'(rho) + da' b'],
+//               Q_t = Y2[rho_d(rho)][b'][hR(rho)]
+// Wave w takes the items t = w, w+4, ...; the four partial tiles are summed
+// through LDS at the end.  Operands are read straight from global memory:
+// along the lanes of one MFMA operand the addresses are consecutive.
+template <int MODE, int NJ>
+__global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __restrict__ P,
+                                                     const double* __restrict__ Q, int rows, int Db, int Dr2, int s,
+                                                     double* __restrict__ out) {
+  __shared__ double red[4][16][16 * NJ];
   const RowGeom::Med& md = f.md;
-  const uint32_t rho = blockIdx.x;
-  const uint32_t rd = pext_dev(rho, md.pos_d_rho), a2 = pext_dev(rho, md.pos_a2);
-  const uint32_t hR = pext_dev(rho, f.hR_pos);
-  double acc[PT];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.y * 16;
+  const int row = r0 + li;
+  v4d acc[NJ];
 #pragma unroll
-  for (int p = 0; p < PT; ++p) acc[p] = 0.0;
-  for (int b2 = 0; b2 < md.db2; ++b2) {
-    __syncthreads();
-    const double* Ag = A + size_t(a2 + md.da2 * b2) * Da * Db;
-    for (int i = threadIdx.x; i < Da * Db; i += blockDim.x) As[i] = Ag[i];
-    const double* Yg = Y2 + ((size_t(rd) * md.db2 + b2) * f.nHR + hR) * Db * s;
-    for (int i = threadIdx.x; i < Db * s; i += blockDim.x) Ys[i] = Yg[i];
-    __syncthreads();
+  for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+  int nitems;
+  uint32_t ld = 0, rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0;
+  if (MODE == 0) {
+    ld = blockIdx.x / md.drd;
+    rd = blockIdx.x % md.drd;
+    nitems = md.dL / md.dld;
+    fixed_bits = pdep_dev(ld, md.pos_d_ell);
+    free_bits = uint32_t(md.dL - 1) & ~md.pos_d_ell;
+  } else {
+    const uint32_t rho = blockIdx.x;
+    rd = pext_dev(rho, md.pos_d_rho);
+    a2 = pext_dev(rho, md.pos_a2);
+    hR = pext_dev(rho, f.hR_pos);
+    nitems = md.db2;
+  }
+  for (int t = w; t < nitems; t += 4) {
+    const double* Pt;
+    const double* Qt;
+    if (MODE == 0) {
+      const uint32_t l = fixed_bits | pdep_dev(uint32_t(t), free_bits);
+      Pt = P + size_t(l) * Db * rows;  // K[l][b][g]: element (g, b) at b*rows + g
+      Qt = Q + ((size_t(rd) * md.db2 + pext_dev(l, md.pos_b2)) * f.nHL + pext_dev(l, f.hL_pos)) * Db * s;
+    } else {
+      Pt = P + size_t(a2 + md.da2 * uint32_t(t)) * rows * Db;  // A[sigma][a][b]
+      Qt = Q + ((size_t(rd) * md.db2 + uint32_t(t)) * f.nHR + hR) * Db * s;
+    }
+    for (int kk = 0; kk < Db; kk += 4) {
+      const int k = kk + lk;
+      double a = 0.0;
+      if (row < rows && k < Db) a = MODE == 0 ? Pt[size_t(k) * rows + row] : Pt[size_t(row) * Db + k];
 #pragma unroll
-    for (int p = 0; p < PT; ++p) {
-      const int idx = threadIdx.x + p * blockDim.x;
-      if (idx < Da * s) {
-        const int a = idx / s, j = idx % s;
-        double t = acc[p];
-        for (int b = 0; b < Db; ++b) t = fma(As[a * Db + b], Ys[b * s + j], t);
-        acc[p] = t;
+      for (int j = 0; j < NJ; ++j) {
+        const int jj = 16 * j + li;
+        const double b = (k < Db && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
+        acc[j] = mfma16(a, b, acc[j]);
       }
     }
   }
-  double* o = out + size_t(rho) * Da * s;
 #pragma unroll
-  for (int p = 0; p < PT; ++p) {
-    const int idx = threadIdx.x + p * blockDim.x;
-    if (idx < Da * s) o[idx] = acc[p];
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][4 * v + lk][16 * j + li] = acc[j][v];
+  __syncthreads();
+  double* o = out + size_t(blockIdx.x) * rows * s;
+  (void)Dr2;
+  for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
+    const int r = i / (16 * NJ), jj = i % (16 * NJ);
+    if (r0 + r < rows && jj < s) o[size_t(r0 + r) * s + jj] = red[0][r][jj] + red[1][r][jj] + red[2][r][jj] + red[3][r][jj];
   }
 }
 
-// W2[rd][b'][hL] (Db x s) = sum_{rho in rd} Wh(h(rho), h'(b',hL)) A[a'(rho)+da'b']^T Y[rho]
-template <int PT>
-__global__ void __launch_bounds__(256) medf_W2_kernel(MedF f, const double* __restrict__ A, int Da, int Db,
-                                                      const double* __restrict__ Y, int s,
-                                                      double* __restrict__ W2) {
-  extern __shared__ double sh[];
-  double* As = sh;             // Da x Db
-  double* Ys = sh + Da * Db;   // Da x s
-  double* wsh = Ys + Da * s;   // 16 horizontal weights
+// Register-fed variants for reductions of at most 32 (bond dimensions up to
+// 32, i.e. chi <= 16 for the new bond): each lane loads exactly the operand
+// elements it feeds to the MFMA, so no LDS staging is needed for stage 1, and
+// the loads of the next item are issued as soon as the current item's stage 1
+// has consumed its registers, overlapping stage 2 and the barriers.
+template <int MODE>
+__device__ __forceinline__ void bin_item(const MedF& f, uint32_t rd, uint32_t b2, uint32_t chunk, int t, int li,
+                                         int nbins, const double* __restrict__ P, const double* __restrict__ Q,
+                                         int Da, int Db, int Kd, int s, const double** Pt, const double** Qt,
+                                         double* wgt) {
   const RowGeom::Med& md = f.md;
-  const uint32_t chunk = blockIdx.x % f.chL;
-  const uint32_t pair = blockIdx.x / f.chL;
+  const uint32_t free_bits = MODE == 0 ? (uint32_t(md.dL - 1) & ~md.pos_b2) : (uint32_t(md.dR - 1) & ~md.pos_d_rho);
+  const uint32_t fixed_bits = MODE == 0 ? pdep_dev(b2, md.pos_b2) : pdep_dev(rd, md.pos_d_rho);
+  const uint32_t item = fixed_bits | pdep_dev(uint32_t(t), free_bits);
+  *wgt = 0.0;
+  if (MODE == 0) {
+    const uint32_t l = item;
+    *Pt = P + size_t(l) * Db * Kd;
+    *Qt = Q + (size_t(pext_dev(l, md.pos_d_ell)) * md.drd + rd) * Kd * s;
+    if (li < nbins) {
+      const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(chunk * 16u + li, f.hR_pos);
+      *wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+    }
+  } else {
+    const uint32_t rho = item;
+    *Pt = P + size_t(pext_dev(rho, md.pos_a2) + md.da2 * b2) * Da * Db;
+    *Qt = Q + size_t(rho) * Da * s;
+    if (li < nbins) {
+      const uint32_t l = pdep_dev(b2, md.pos_b2) | pdep_dev(chunk * 16u + li, f.hL_pos);
+      *wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+    }
+  }
+}
+
+template <int MODE, int NJ>
+__global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __restrict__ P,
+                                                     const double* __restrict__ Q, int Da, int Db, int Kd, int s,
+                                                     double* __restrict__ out) {
+  constexpr int KK = 8, QS = 16 * NJ;  // reduction <= 4 * KK
+  __shared__ double Ts[4][16][QS];
+  __shared__ double Ws[4][16];
+  const RowGeom::Med& md = f.md;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nch = MODE == 0 ? f.chR : f.chL, nH = MODE == 0 ? f.nHR : f.nHL;
+  const uint32_t chunk = blockIdx.x % nch, pair = blockIdx.x / nch;
   const uint32_t rd = pair / md.db2, b2 = pair % md.db2;
-  const uint32_t b2_bits = pdep_dev(b2, md.pos_b2);
-  const int nb = min(16, f.nHL - int(chunk) * 16);
-  double acc[16][PT];
+  const int b0 = blockIdx.y * 16;
+  const int nbins = min(16, nH - int(chunk) * 16);
+  const int nitems = MODE == 0 ? md.dL / md.db2 : md.dR / md.drd;
+  const int nkk = (Kd + 3) >> 2;
+  const int b = b0 + li;
+  double pa[KK], qb[KK][NJ], wr = 0.0;
+  auto fetch = [&](int t) {
+    if (t >= nitems) return;
+    const double* Pt;
+    const double* Qt;
+    bin_item<MODE>(f, rd, b2, chunk, t, li, nbins, P, Q, Da, Db, Kd, s, &Pt, &Qt, &wr);
 #pragma unroll
-  for (int h = 0; h < 16; ++h)
+    for (int kk = 0; kk < KK; ++kk) {
+      const int k = 4 * kk + lk;
+      const bool ok = kk < nkk && k < Kd;
+      pa[kk] = (ok && b < Db) ? (MODE == 0 ? Pt[size_t(b) * Kd + k] : Pt[size_t(k) * Db + b]) : 0.0;
 #pragma unroll
-    for (int p = 0; p < PT; ++p) acc[h][p] = 0.0;
-  const uint32_t freeR = uint32_t(md.dR - 1) & ~md.pos_d_rho;
-  const int nr = md.dR / md.drd;
-  for (int fr = 0; fr < nr; ++fr) {
-    const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(uint32_t(fr), freeR);
-    const uint32_t a2 = pext_dev(rho, md.pos_a2);
-    const uint32_t hr = pext_dev(rho, md.pos_h_rho);
-    __syncthreads();
-    const double* Ag = A + size_t(a2 + md.da2 * b2) * Da * Db;
-    for (int i = threadIdx.x; i < Da * Db; i += blockDim.x) As[i] = Ag[i];
-    const double* Yg = Y + size_t(rho) * Da * s;
-    for (int i = threadIdx.x; i < Da * s; i += blockDim.x) Ys[i] = Yg[i];
-    if (int(threadIdx.x) < nb) {
-      const uint32_t l = b2_bits | pdep_dev(chunk * 16u + threadIdx.x, f.hL_pos);
-      wsh[threadIdx.x] = md.Wh[hr * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PT; ++p) {
-      const int idx = threadIdx.x + p * blockDim.x;
-      if (idx < Db * s) {
-        const int b = idx / s, j = idx % s;
-        double t = 0.0;
-        for (int a = 0; a < Da; ++a) t = fma(As[a * Db + b], Ys[a * s + j], t);
-#pragma unroll
-        for (int h = 0; h < 16; ++h)
-          if (h < nb) acc[h][p] = fma(wsh[h], t, acc[h][p]);
+      for (int j = 0; j < NJ; ++j) {
+        const int jj = 16 * j + li;
+        qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
       }
     }
+  };
+  v4d acc[4][NJ];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  fetch(w);
+  for (int t0 = 0; t0 < nitems; t0 += 4) {
+    const int t = t0 + w;
+    v4d tt[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) tt[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const bool live = t < nitems;
+    const double wcur = live ? wr : 0.0;
+    if (live) {
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk)
+        if (kk < nkk)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) tt[j] = mfma16(pa[kk], qb[kk][j], tt[j]);
+    }
+    fetch(t + 4);  // next item's operands load during stage 2
+    __syncthreads();  // the previous round's stage 2 is done with Ts and Ws
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ts[w][4 * v + lk][16 * j + li] = tt[j][v];
+    if (lane < 16) Ws[w][lane] = wcur;
+    __syncthreads();
+    const double a2 = Ws[lk][li];
+#pragma unroll
+    for (int bl = 0; bl < 4; ++bl)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[bl][j] = mfma16(a2, Ts[lk][4 * w + bl][16 * j + li], acc[bl][j]);
   }
-  double* out = W2 + (size_t(pair) * f.nHL + chunk * 16u) * Db * s;
+  double* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
 #pragma unroll
-  for (int p = 0; p < PT; ++p) {
-    const int idx = threadIdx.x + p * blockDim.x;
-    if (idx < Db * s)
+  for (int bl = 0; bl < 4; ++bl) {
+    const int bb = b0 + 4 * w + bl;
+    if (bb >= Db) continue;
 #pragma unroll
-      for (int h = 0; h < 16; ++h)
-        if (h < nb) out[size_t(h) * Db * s + idx] = acc[h][p];
+    for (int j = 0; j < NJ; ++j) {
+      const int jj = 16 * j + li;
+      if (jj >= s) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int h = 4 * v + lk;
+        if (h < nbins) o[(size_t(h) * Db + bb) * s + jj] = acc[bl][j][v];
+      }
+    }
   }
 }
 
-// G2[ld][rd] (Dg x s) = sum_{l in ld} K[l]^T W2[rd][b'(l)][hL(l)]
-template <int PT>
-__global__ void __launch_bounds__(256) medf_G2_kernel(MedF f, const double* __restrict__ Kc, int Db, int Dg,
-                                                      const double* __restrict__ W2, int s,
-                                                      double* __restrict__ G2) {
-  extern __shared__ double sh[];
-  double* Ks = sh;             // Db x Dg
-  double* Ws = sh + Db * Dg;   // Db x s
+// medf_acc_mfma with the next item's operands prefetched into registers
+// (Db <= 32).
+template <int MODE, int NJ>
+__global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __restrict__ P,
+                                                     const double* __restrict__ Q, int rows, int Db, int Dr2, int s,
+                                                     double* __restrict__ out) {
+  constexpr int KK = 8;
+  __shared__ double red[4][16][16 * NJ];
   const RowGeom::Med& md = f.md;
-  const uint32_t ld = blockIdx.x / md.drd, rd = blockIdx.x % md.drd;
-  double acc[PT];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.y * 16;
+  const int row = r0 + li;
+  const int nkk = (Db + 3) >> 2;
+  int nitems;
+  uint32_t rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0;
+  if (MODE == 0) {
+    const uint32_t ld = blockIdx.x / md.drd;
+    rd = blockIdx.x % md.drd;
+    nitems = md.dL / md.dld;
+    fixed_bits = pdep_dev(ld, md.pos_d_ell);
+    free_bits = uint32_t(md.dL - 1) & ~md.pos_d_ell;
+  } else {
+    const uint32_t rho = blockIdx.x;
+    rd = pext_dev(rho, md.pos_d_rho);
+    a2 = pext_dev(rho, md.pos_a2);
+    hR = pext_dev(rho, f.hR_pos);
+    nitems = md.db2;
+  }
+  // two statically named register buffers (a runtime buffer index would put
+  // the arrays in scratch memory)
+  double pa0[KK], qb0[KK][NJ], pa1[KK], qb1[KK][NJ];
+  auto fetch = [&](int t, double (&pa)[KK], double (&qb)[KK][NJ]) {
+    if (t >= nitems) return;
+    const double* Pt;
+    const double* Qt;
+    if (MODE == 0) {
+      const uint32_t l = fixed_bits | pdep_dev(uint32_t(t), free_bits);
+      Pt = P + size_t(l) * Db * rows;
+      Qt = Q + ((size_t(rd) * md.db2 + pext_dev(l, md.pos_b2)) * f.nHL + pext_dev(l, f.hL_pos)) * Db * s;
+    } else {
+      Pt = P + size_t(a2 + md.da2 * uint32_t(t)) * rows * Db;
+      Qt = Q + ((size_t(rd) * md.db2 + uint32_t(t)) * f.nHR + hR) * Db * s;
+    }
 #pragma unroll
-  for (int p = 0; p < PT; ++p) acc[p] = 0.0;
-  const uint32_t freeL = uint32_t(md.dL - 1) & ~md.pos_d_ell;
-  const int nl = md.dL / md.dld;
-  for (int fl = 0; fl < nl; ++fl) {
-    const uint32_t l = pdep_dev(ld, md.pos_d_ell) | pdep_dev(uint32_t(fl), freeL);
-    const uint32_t b2 = pext_dev(l, md.pos_b2), hL = pext_dev(l, f.hL_pos);
-    __syncthreads();
-    for (int i = threadIdx.x; i < Db * Dg; i += blockDim.x) Ks[i] = Kc[size_t(l) * Db * Dg + i];
-    const double* Wg = W2 + ((size_t(rd) * md.db2 + b2) * f.nHL + hL) * Db * s;
-    for (int i = threadIdx.x; i < Db * s; i += blockDim.x) Ws[i] = Wg[i];
-    __syncthreads();
+    for (int kk = 0; kk < KK; ++kk) {
+      const int k = 4 * kk + lk;
+      const bool ok = kk < nkk && k < Db;
+      pa[kk] = (ok && row < rows) ? (MODE == 0 ? Pt[size_t(k) * rows + row] : Pt[size_t(row) * Db + k]) : 0.0;
 #pragma unroll
-    for (int p = 0; p < PT; ++p) {
-      const int idx = threadIdx.x + p * blockDim.x;
-      if (idx < Dg * s) {
-        const int g = idx / s, j = idx % s;
-        double t = acc[p];
-        for (int b = 0; b < Db; ++b) t = fma(Ks[b * Dg + g], Ws[b * s + j], t);
-        acc[p] = t;
+      for (int j = 0; j < NJ; ++j) {
+        const int jj = 16 * j + li;
+        qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
       }
     }
-  }
-  double* o = G2 + size_t(blockIdx.x) * Dg * s;
+  };
+  v4d acc[NJ];
 #pragma unroll
-  for (int p = 0; p < PT; ++p) {
-    const int idx = threadIdx.x + p * blockDim.x;
-    if (idx < Dg * s) o[idx] = acc[p];
+  for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto use = [&](const double (&pa)[KK], const double (&qb)[KK][NJ]) {
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+      if (kk < nkk)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = mfma16(pa[kk], qb[kk][j], acc[j]);
+  };
+  fetch(w, pa0, qb0);
+  for (int t = w; t < nitems; t += 8) {
+    fetch(t + 4, pa1, qb1);
+    use(pa0, qb0);
+    if (t + 4 >= nitems) break;
+    fetch(t + 8, pa0, qb0);
+    use(pa1, qb1);
   }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][4 * v + lk][16 * j + li] = acc[j][v];
+  __syncthreads();
+  double* o = out + size_t(blockIdx.x) * rows * s;
+  (void)Dr2;
+  for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
+    const int r = i / (16 * NJ), jj = i % (16 * NJ);
+    if (r0 + r < rows && jj < s) o[size_t(r0 + r) * s + jj] = red[0][r][jj] + red[1][r][jj] + red[2][r][jj] + red[3][r][jj];
+  }
+}
+
+static size_t medf_bin_lds(int Kd, int nj) {
+  const size_t Kp = size_t((Kd + 3) & ~3);
+  size_t K2 = 1;
+  while (K2 < Kp) K2 <<= 1;
+  return (4 * 16 * (K2 + 1) + 4 * Kp * 16 * nj + 4 * 16 * 16 * nj + 64) * sizeof(double);
 }
 
 // site[sigma][i][g] = V[(sigma*Dg + g)][i]   (V: n_cols x t)
@@ -459,26 +687,6 @@ static void make_medf(const RowGeom::Med& md, MedF* f) {
   f->chL = (f->nHL + 15) / 16;
 }
 
-static int pick_pt(int64_t n) {
-  const int opts[] = {1, 2, 4, 6, 8, 12};
-  for (int p : opts)
-    if (int64_t(p) * 256 >= n) return p;
-  return -1;
-}
-
-#define TNB_PT_CASE(P, KERNEL, GRID, SHM, ST, ...) \
-    case P: allow_big_lds(KERNEL<P>, SHM); hipLaunchKernelGGL(KERNEL<P>, GRID, dim3(256), SHM, ST, __VA_ARGS__); break;
-#define TNB_PT_DISPATCH(PTV, KERNEL, GRID, SHM, ST, ...)                                      \
-  switch (PTV) {                                                                               \
-    TNB_PT_CASE(1, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
-    TNB_PT_CASE(2, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
-    TNB_PT_CASE(4, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
-    TNB_PT_CASE(6, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
-    TNB_PT_CASE(8, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                         \
-    TNB_PT_CASE(12, KERNEL, GRID, SHM, ST, __VA_ARGS__)                                        \
-    default: fail(TNB_EUNSUPPORTED, "factored mediating tile too large for the register budget"); \
-  }
-
 constexpr size_t kMaxLds = 163840;  // gfx950: 160 KiB of LDS per workgroup
 
 static void check_lds(size_t bytes) {
@@ -492,6 +700,20 @@ static void allow_big_lds(K kernel, size_t bytes) {
     HIPC(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
 }
+
+#define TNB_NJ_CASE(NJV, KERNEL, MODE, GRID, SHM, ST, ...)                                   \
+  case NJV:                                                                                  \
+    allow_big_lds(KERNEL<MODE, NJV>, SHM);                                                  \
+    hipLaunchKernelGGL((KERNEL<MODE, NJV>), GRID, dim3(256), SHM, ST, __VA_ARGS__);          \
+    break;
+#define TNB_NJ_LAUNCH(NJ, KERNEL, MODE, GRID, SHM, ST, ...)                                    \
+  switch (NJ) {                                                                              \
+    TNB_NJ_CASE(1, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
+    TNB_NJ_CASE(2, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
+    TNB_NJ_CASE(3, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
+    TNB_NJ_CASE(4, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
+    default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");                   \
+  }
 
 // Copy `width` columns starting at c0 of a row-major (n x lds) matrix into
 // columns d0.. of a row-major (n x ldd) matrix.
@@ -517,9 +739,10 @@ struct Zipper {
   // Widest sketch block whose diagram tiles fit the LDS and register budget.
   static int block_width(int Da, int Db, int Dg, int s) {
     const int mx = std::max(Da, std::max(Db, Dg));
-    int w = s;
+    int w = std::min(s, 64);
     while (w > 1 && (int64_t(mx) * w > 12 * 256 ||
-                     (size_t(mx) * mx + size_t(mx) * w + 16) * sizeof(double) > kMaxLds))
+                     (size_t(mx) * mx + size_t(mx) * w + 16) * sizeof(double) > kMaxLds ||
+                     medf_bin_lds(std::max(Da, Dg), (w + 15) / 16) > kMaxLds))
       --w;
     return w;
   }
@@ -584,28 +807,35 @@ struct Zipper {
                int64_t(Dg) * s, int64_t(md.drd) * Dg * s, 1.0, 0.0, ws, st);
       MedF f;
       make_medf(md, &f);
+      ensure(Yf, size_t(md.drd) * md.db2 * f.nHR * Db * s);
+      const int nj = (s + 15) / 16;
       {
-        ensure(Yf, size_t(md.drd) * md.db2 * f.nHR * Db * s);
-        const int pt1 = pick_pt(int64_t(Db) * s), pt2 = pick_pt(int64_t(Da) * s);
-        check_lds((size_t(Db) * Dg + size_t(Dg) * s + 16) * sizeof(double));
-        check_lds((size_t(Da) * Db + size_t(Db) * s) * sizeof(double));
-{
-        KTimer _t1("medf_Y2", st,
-                   double(md.drd) * md.dL * (2.0 * Db * Dg * s * f.chR + 2.0 * f.nHR * Db * s),
+        const size_t shm = medf_bin_lds(Dg, nj);
+        check_lds(shm);
+        KTimer _t1("medf_Y2", st, double(md.drd) * md.dL * (2.0 * Db * Dg * s + 2.0 * f.nHR * Db * s),
                    8.0 * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
                           double(md.drd) * md.db2 * f.nHR * Db * s));
-        TNB_PT_DISPATCH(pt1, medf_Y2_kernel, dim3(md.drd * md.db2 * f.chR),
-                        (size_t(Db) * Dg + size_t(Dg) * s + 16) * sizeof(double), st, f, conn.p, Db, Dg, X2.p, s, Yf.p);
-        HIPC(hipGetLastError());
+        if (Dg <= 32) {
+          TNB_NJ_LAUNCH(nj, medf_bin_pipe, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), 0, st, f, conn.p,
+                        X2.p, Da, Db, Dg, s, Yf.p);
+        } else {
+          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, conn.p,
+                        X2.p, Da, Db, Dg, s, Yf.p);
         }
-{
+        HIPC(hipGetLastError());
+      }
+      {
         KTimer _t2("medf_out", st, double(md.dR) * md.db2 * 2.0 * Da * Db * s,
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
                           double(md.dR) * Da * s));
-        TNB_PT_DISPATCH(pt2, medf_out_kernel, dim3(md.dR),
-                        (size_t(Da) * Db + size_t(Db) * s) * sizeof(double), st, f, A.data.p, Da, Db, Yf.p, s, out);
-        HIPC(hipGetLastError());
+        if (Db <= 32) {
+          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, A.data.p, Yf.p, Da, Db, 0, s,
+                        out);
+        } else {
+          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, A.data.p, Yf.p, Da, Db, 0, s,
+                        out);
         }
+        HIPC(hipGetLastError());
       }
     }
   }
@@ -638,28 +868,35 @@ struct Zipper {
       double* G2 = X2.p;  // [ld][rd][Dg*s]
       MedF f;
       make_medf(md, &f);
+      ensure(Yf, size_t(md.drd) * md.db2 * f.nHL * Db * s);
+      const int nj = (s + 15) / 16;
       {
-        ensure(Yf, size_t(md.drd) * md.db2 * f.nHL * Db * s);
-        const int pt1 = pick_pt(int64_t(Db) * s), pt2 = pick_pt(int64_t(Dg) * s);
-        check_lds((size_t(Da) * Db + size_t(Da) * s + 16) * sizeof(double));
-        check_lds((size_t(Db) * Dg + size_t(Db) * s) * sizeof(double));
-{
-        KTimer _t1("medf_W2", st,
-                   double(md.dR) * md.db2 * (2.0 * Da * Db * s * f.chL + 2.0 * f.nHL * Db * s),
+        const size_t shm = medf_bin_lds(Da, nj);
+        check_lds(shm);
+        KTimer _t1("medf_W2", st, double(md.dR) * md.db2 * (2.0 * Da * Db * s + 2.0 * f.nHL * Db * s),
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
                           double(md.drd) * md.db2 * f.nHL * Db * s));
-        TNB_PT_DISPATCH(pt1, medf_W2_kernel, dim3(md.drd * md.db2 * f.chL),
-                        (size_t(Da) * Db + size_t(Da) * s + 16) * sizeof(double), st, f, A.data.p, Da, Db, Yin, s, Yf.p);
-        HIPC(hipGetLastError());
+        if (Da <= 32) {
+          TNB_NJ_LAUNCH(nj, medf_bin_pipe, 1, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), 0, st, f, A.data.p,
+                        Yin, Da, Db, Da, s, Yf.p);
+        } else {
+          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 1, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), shm, st, f, A.data.p,
+                        Yin, Da, Db, Da, s, Yf.p);
         }
-{
+        HIPC(hipGetLastError());
+      }
+      {
         KTimer _t2("medf_G2", st, double(md.dL) * md.drd * 2.0 * Db * Dg * s,
                    8.0 * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
                           double(md.dld) * md.drd * Dg * s));
-        TNB_PT_DISPATCH(pt2, medf_G2_kernel, dim3(md.dld * md.drd),
-                        (size_t(Db) * Dg + size_t(Db) * s) * sizeof(double), st, f, conn.p, Db, Dg, Yf.p, s, G2);
-        HIPC(hipGetLastError());
+        if (Db <= 32) {
+          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, conn.p, Yf.p, Dg, Db,
+                        0, s, G2);
+        } else {
+          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, conn.p, Yf.p, Dg, Db,
+                          0, s, G2);
         }
+        HIPC(hipGetLastError());
       }
       // H[ld] (db x Dg*s) = Wdl (db x drd) . G2[ld]
       la::gemm(md.dld, md.db, Dg * s, md.drd, la::View{md.Wdl, md.Wdl_sp, md.Wdl_sq, 0},
