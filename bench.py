@@ -32,6 +32,26 @@ WORKLOADS = {
 
 PEAK = {"alu_fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
+# Valid only for the kernel source they were taken on (hash of its file).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "medf_Y2_zephyr_z2_t4_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2411_16431_amd", "csrc", "env.hip")
+
+
+def measured_traffic(kernel, workload):
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        with open(KERNEL_SRC, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -41,6 +61,8 @@ def parse():
     ap.add_argument("--workload", default="zephyr_z2_t4_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--power-iters", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a plain 1 GiB device copy, the reference dispatch for HBM byte counters")
     return ap.parse_args()
 
 
@@ -176,7 +198,9 @@ def main():
         avg_s = ms / 1000.0 / n
         roof = {"bound": "alu", "kernel": dom, "achieved": fl / n / avg_s / 1e12,
                 "peak": PEAK["alu_fp64_tflops"], "unit": "TFLOP/s",
-                "frac": fl / n / avg_s / 1e12 / PEAK["alu_fp64_tflops"], "traffic": None,
+                "frac": fl / n / avg_s / 1e12 / PEAK["alu_fp64_tflops"],
+                "traffic": measured_traffic(dom, args.workload), "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": by / n,
                 "avg_ms": ms / n, "launches_per_step": n / args.steps,
                 "share_of_step": ms / args.steps / ms_step}
     counts = {"site": (prof.get("site_apply", (0, 0))[1] + prof.get("site_applyT", (0, 0))[1]) / args.steps,
@@ -202,6 +226,14 @@ def main():
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        n = 1 << 27  # 1 GiB of FP64
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy calibration: %d bytes read, %d bytes written" % (8 * n, 8 * n), file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":
