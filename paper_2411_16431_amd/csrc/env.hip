@@ -462,6 +462,7 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
   const int nitems = MODE == 0 ? md.dL / md.db2 : md.dR / md.drd;
   const int nkk = (Kd + 3) >> 2;
   const int b = b0 + li;
+  const int j0 = blockIdx.z * 16 * NJ;  // first sketch column of this workgroup
   double pa[KK], qb[KK][NJ], wr = 0.0;
   auto fetch = [&](int t) {
     if (t >= nitems) return;
@@ -475,7 +476,7 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
       pa[kk] = (ok && b < Db) ? (MODE == 0 ? Pt[size_t(b) * Kd + k] : Pt[size_t(k) * Db + b]) : 0.0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const int jj = 16 * j + li;
+        const int jj = j0 + 16 * j + li;
         qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
       }
     }
@@ -521,7 +522,7 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
     if (bb >= Db) continue;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int jj = 16 * j + li;
+      const int jj = j0 + 16 * j + li;
       if (jj >= s) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -546,6 +547,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
   const int r0 = blockIdx.y * 16;
   const int row = r0 + li;
   const int nkk = (Db + 3) >> 2;
+  const int j0 = blockIdx.z * 16 * NJ;  // first sketch column of this workgroup
   int nitems;
   uint32_t rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0;
   if (MODE == 0) {
@@ -583,7 +585,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
       pa[kk] = (ok && row < rows) ? (MODE == 0 ? Pt[size_t(k) * rows + row] : Pt[size_t(row) * Db + k]) : 0.0;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const int jj = 16 * j + li;
+        const int jj = j0 + 16 * j + li;
         qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
       }
     }
@@ -615,7 +617,8 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
   (void)Dr2;
   for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
     const int r = i / (16 * NJ), jj = i % (16 * NJ);
-    if (r0 + r < rows && jj < s) o[size_t(r0 + r) * s + jj] = red[0][r][jj] + red[1][r][jj] + red[2][r][jj] + red[3][r][jj];
+    if (r0 + r < rows && j0 + jj < s)
+      o[size_t(r0 + r) * s + j0 + jj] = red[0][r][jj] + red[1][r][jj] + red[2][r][jj] + red[3][r][jj];
   }
 }
 
@@ -816,8 +819,10 @@ struct Zipper {
                    8.0 * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
                           double(md.drd) * md.db2 * f.nHR * Db * s));
         if (Dg <= 32) {
-          TNB_NJ_LAUNCH(nj, medf_bin_pipe, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), 0, st, f, conn.p,
-                        X2.p, Da, Db, Dg, s, Yf.p);
+          // one 16-column sketch tile per workgroup keeps the register count at
+          // three waves per SIMD
+          hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16, nj), dim3(256), 0,
+                             st, f, conn.p, X2.p, Da, Db, Dg, s, Yf.p);
         } else {
           TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, conn.p,
                         X2.p, Da, Db, Dg, s, Yf.p);
@@ -829,6 +834,7 @@ struct Zipper {
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
                           double(md.dR) * Da * s));
         if (Db <= 32) {
+          // all sketch columns in one workgroup: the P operand is loaded once
           TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, A.data.p, Yf.p, Da, Db, 0, s,
                         out);
         } else {
@@ -877,8 +883,8 @@ struct Zipper {
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
                           double(md.drd) * md.db2 * f.nHL * Db * s));
         if (Da <= 32) {
-          TNB_NJ_LAUNCH(nj, medf_bin_pipe, 1, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), 0, st, f, A.data.p,
-                        Yin, Da, Db, Da, s, Yf.p);
+          hipLaunchKernelGGL((medf_bin_pipe<1, 1>), dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16, nj), dim3(256), 0,
+                             st, f, A.data.p, Yin, Da, Db, Da, s, Yf.p);
         } else {
           TNB_NJ_LAUNCH(nj, medf_bin_mfma, 1, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), shm, st, f, A.data.p,
                         Yin, Da, Db, Da, s, Yf.p);
