@@ -6,7 +6,9 @@ not touch the GPU; the first call that needs the library loads it and fails
 loudly if it has not been built.
 """
 from .api import (TnbError, energies, Clusters, Env, Beam, EnvOptions, solve, library_path,
-                  exported_symbols, profile_enable, profile_query, profile_names)
+                  exported_symbols, profile_enable, profile_query, profile_names, FirstRowLogZ,
+                  first_row_layout)
 
 __all__ = ["TnbError", "energies", "Clusters", "Env", "Beam", "EnvOptions", "solve",
-           "library_path", "exported_symbols", "profile_enable", "profile_query", "profile_names"]
+           "library_path", "exported_symbols", "profile_enable", "profile_query", "profile_names",
+           "FirstRowLogZ", "first_row_layout"]

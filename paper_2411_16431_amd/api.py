@@ -242,6 +242,69 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
                 spin_marginals=marg)
 
 
+def first_row_layout(inst, beta=1.0):
+    """(spins, edges) of the first row of clusters: the inputs of FirstRowLogZ."""
+    env = Env(Clusters(inst, beta), EnvOptions(chi=1))
+    return Beam(env, 1).row_layout()
+
+
+def _first_row_logz_and_moments(inst, beta, opts, h_row, J_row, spins, edges):
+    import copy
+    k = copy.copy(inst)
+    k.h = np.array(inst.h, dtype=np.float64, copy=True)
+    k.J = np.array(inst.J, dtype=np.float64, copy=True)
+    k.h[spins] = h_row
+    k.J[edges] = J_row
+    env = Env(Clusters(k, beta), opts)
+    m1, m2 = Beam(env, 1).row_moments()
+    return env.logZ, m1[0], m2[0]
+
+
+class FirstRowLogZ:
+    """log Z of an instance as a function of the fields and intra-cluster
+    couplings of its first row of clusters (Eq. 10), with a hand-written
+    backward: the adjoint of the row contraction gives
+    d log Z / d h_i = -beta <s_i> and d log Z / d J_ij = -beta <s_i s_j>
+    (tnb_row_moments at the first step).  The boundary MPS below the first row
+    does not depend on these inputs, so the gradient is complete for them.
+
+    apply(h_row, J_row, inst, beta, opts) with h_row, J_row float64 tensors in
+    the order of first_row_layout(inst)."""
+
+    @staticmethod
+    def apply(h_row, J_row, inst, beta, opts):
+        return _first_row_fn().apply(h_row, J_row, inst, beta, opts)
+
+
+_FN = None
+
+
+def _first_row_fn():
+    global _FN
+    if _FN is None:
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, h_row, J_row, inst, beta, opts):
+                spins, edges = first_row_layout(inst, beta)
+                if h_row.numel() != len(spins) or J_row.numel() != len(edges):
+                    raise ValueError("h_row/J_row must follow first_row_layout(inst)")
+                lz, m1, m2 = _first_row_logz_and_moments(inst, beta, opts, h_row.detach().cpu().numpy(),
+                                                         J_row.detach().cpu().numpy(), spins, edges)
+                ctx.beta = float(beta)
+                ctx.save_for_backward(m1.to(h_row.device), m2.to(J_row.device))
+                return torch.tensor(lz, dtype=torch.float64, device=h_row.device)
+
+            @staticmethod
+            def backward(ctx, g):
+                m1, m2 = ctx.saved_tensors
+                return -ctx.beta * g * m1, -ctx.beta * g * m2, None, None, None
+
+        _FN = _F
+    return _FN
+
+
 def profile_enable(on=True):
     """Start (clearing earlier records) or stop per-kernel event timing."""
     _check(L.lib().tnb_profile_enable(1 if on else 0))

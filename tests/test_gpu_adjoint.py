@@ -126,3 +126,39 @@ def test_row_moments_argument_checks():
         beam.step()
     sp = ctypes.c_int32()
     assert L.lib().tnb_row_layout(beam._h, ctypes.byref(sp), None, None, None, 0) == -1
+
+
+@pytest.mark.parametrize("kind,kw,chi", [("king", dict(R=2, C=3, a=2), 64), ("zephyr", dict(m=1, t=2), 64),
+                                         ("king", dict(R=3, C=3, a=2), 3)])
+def test_first_row_logz_gradient(kind, kw, chi):
+    # the autograd Function's backward (the HIP adjoint) against central finite
+    # differences of its forward (log Z from tnb_contract_env), and, with an
+    # exact environment, against brute-force <s_i> and <s_i s_j>
+    pk, torch = _gpu()
+    from oracle import ising
+    inst = make_instance(kind, 404, jdist="uniform", hdist="uniform0.1", **kw)
+    beta = 0.8
+    opts = pk.EnvOptions(chi=chi, power_iters=2, seed=3, cut=1e-7)
+    sp, ed = pk.first_row_layout(inst, beta)
+    h = torch.tensor(inst.h[sp], dtype=torch.float64, requires_grad=True)
+    J = torch.tensor(inst.J[ed], dtype=torch.float64, requires_grad=True)
+    lz = pk.FirstRowLogZ.apply(h, J, inst, beta, opts)
+    lz.backward()
+    gh, gJ = h.grad.numpy(), J.grad.numpy()
+    eps = 1e-5
+    f = lambda hh, JJ: pk.FirstRowLogZ.apply(torch.tensor(hh), torch.tensor(JJ), inst, beta, opts).item()
+    h0, J0 = inst.h[sp].copy(), inst.J[ed].copy()
+    for i in (0, len(sp) // 2, len(sp) - 1):
+        dh = np.zeros_like(h0)
+        dh[i] = eps
+        fd = (f(h0 + dh, J0) - f(h0 - dh, J0)) / (2 * eps)
+        assert abs(fd - gh[i]) <= 1e-6 * (1 + abs(fd)), (i, fd, gh[i])
+    for e in (0, len(ed) - 1):
+        dJ = np.zeros_like(J0)
+        dJ[e] = eps
+        fd = (f(h0, J0 + dJ) - f(h0, J0 - dJ)) / (2 * eps)
+        assert abs(fd - gJ[e]) <= 1e-6 * (1 + abs(fd)), (e, fd, gJ[e])
+    if chi == 64:
+        bf = ising.brute_force(inst, beta)
+        assert np.allclose(-gh / beta, bf["m1"][sp], atol=1e-8)
+        assert np.allclose(-gJ / beta, bf["m2"][ed], atol=1e-8)
