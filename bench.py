@@ -30,7 +30,8 @@ WORKLOADS = {
                                hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
 }
 
-PEAK = {"alu_fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+PEAK = {"alu_fp64_tflops": 78.6, "hbm_gbs": 8000.0}  # FP64 vector and FP64 MFMA peaks are equal
+MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_G2", "medf_out", "renv_V", "adj_v"}
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
@@ -196,7 +197,7 @@ def main():
     if dom:
         ms, n, fl, by = prof[dom]
         avg_s = ms / 1000.0 / n
-        roof = {"bound": "alu", "kernel": dom, "achieved": fl / n / avg_s / 1e12,
+        roof = {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": dom, "achieved": fl / n / avg_s / 1e12,
                 "peak": PEAK["alu_fp64_tflops"], "unit": "TFLOP/s",
                 "frac": fl / n / avg_s / 1e12 / PEAK["alu_fp64_tflops"],
                 "traffic": measured_traffic(dom, args.workload), "traffic_unit": "bytes per launch",
