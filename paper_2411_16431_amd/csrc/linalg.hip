@@ -80,9 +80,22 @@ static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double
   HIPC(hipGetLastError());
 }
 
+void gemm_mfma(int batch, int M, int N, int K, const Operand& A, const Operand& B, double* C, Ix cr, Ix cc,
+               int64_t cbs, double alpha, double beta, hipStream_t s, const char* timer);
+
 void gemm(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t ldc, int64_t bsc,
           double alpha, double beta, Scratch& ws, hipStream_t s) {
   if (batch <= 0 || M <= 0 || N <= 0) return;
+  // Enough output tiles to fill the chip: the matrix-core kernel, which sums
+  // all of K per tile.  Few tiles over a long K (Gram matrices): the split-K
+  // vector kernel below.
+  const int64_t mt = int64_t((M + 127) / 128) * ((N + 63) / 64) * batch;
+  if (mt >= 128 && K < (int64_t(1) << 31)) {
+    Operand a{A.p, A.bs, Ix{0, 0, A.rs}, Ix{0, 0, A.cs}};
+    Operand b{B.p, B.bs, Ix{0, 0, B.rs}, Ix{0, 0, B.cs}};
+    gemm_mfma(batch, M, N, int(K), a, b, C, Ix{0, 0, ldc}, Ix{0, 0, 1}, bsc, alpha, beta, s, "gemm");
+    return;
+  }
   const int maxb = 32768;
   for (int b0 = 0; b0 < batch; b0 += maxb) {
     const int nb = batch - b0 < maxb ? batch - b0 : maxb;
@@ -94,10 +107,10 @@ void gemm(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t
 // ---------------------------------------------------------------------------
 // Cyclic Jacobi (Golub & Van Loan, Sec. 8.5) with the round-robin ordering:
 // each round applies up to s/2 disjoint rotations at once.
-__global__ void __launch_bounds__(1024) jacobi_kernel(double* __restrict__ G, int s,
-                                                      double* __restrict__ V,
-                                                      double* __restrict__ lam) {
-  extern __shared__ double sh[];
+// G and V are the working matrices (global memory, or LDS in the _lds
+// variant); sh is 2560 doubles of LDS scratch.
+__device__ void jacobi_body(double* __restrict__ G, int s, double* __restrict__ V, double* __restrict__ lam,
+                            double* __restrict__ sh) {
   double* cs = sh;                 // [m/2] cosines
   double* sn = sh + 512;           // [m/2] sines
   int* pp = reinterpret_cast<int*>(sh + 1024);
@@ -199,12 +212,46 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(double* __restrict__ G, in
   }
 }
 
+__global__ void __launch_bounds__(1024) jacobi_kernel(double* __restrict__ G, int s, double* __restrict__ V,
+                                                      double* __restrict__ lam) {
+  extern __shared__ double sh[];
+  jacobi_body(G, s, V, lam, sh);
+}
+
+// The same with G and V held in LDS (2 s^2 + 2560 doubles): every rotation
+// round reads and writes LDS instead of L2.
+__global__ void __launch_bounds__(1024) jacobi_lds_kernel(double* __restrict__ Gg, int s, double* __restrict__ Vg,
+                                                          double* __restrict__ lam) {
+  extern __shared__ double sh[];
+  double* G = sh + 2560;
+  double* V = G + s * s;
+  for (int i = threadIdx.x; i < s * s; i += blockDim.x) G[i] = Gg[i];
+  __syncthreads();
+  jacobi_body(G, s, V, lam, sh);
+  __syncthreads();
+  for (int i = threadIdx.x; i < s * s; i += blockDim.x) Vg[i] = V[i];
+}
+
+static bool lds_fits(int m) { return (2560 + 2 * size_t(m) * m) * sizeof(double) <= 163840; }
+
+template <class K>
+static void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    HIPC(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(bytes)));
+}
+
 void eigh(double* G, int s, double* V, double* lam, hipStream_t st) {
   if (s <= 0) return;
   if (s > 1000) fail(TNB_EUNSUPPORTED, "eigensolver limited to 1000 x 1000");
-  size_t shm = 2560 * sizeof(double);
   KTimer _t("eigh", st, 0.0, 16.0 * s * s);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), shm, st, G, s, V, lam);
+  if (lds_fits(s)) {
+    const size_t shm = (2560 + 2 * size_t(s) * s) * sizeof(double);
+    allow_lds(jacobi_lds_kernel, shm);
+    hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(1024), shm, st, G, s, V, lam);
+  } else {
+    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 2560 * sizeof(double), st, G, s, V, lam);
+  }
   HIPC(hipGetLastError());
 }
 
@@ -223,9 +270,10 @@ __global__ void inv_sqrt_weights_kernel(const double* __restrict__ V, const doub
 // columns pairwise, round-robin over disjoint pairs.  Singular values are
 // accurate to eps * sigma_max.  Outputs sorted descending: S[m], U (m x m,
 // columns of A normalised; zero for sigma = 0), V (m x m).
-__global__ void __launch_bounds__(1024) hestenes_kernel(double* __restrict__ A, int m, double* __restrict__ U,
-                                                        double* __restrict__ V, double* __restrict__ S) {
-  extern __shared__ double sh[];
+// A and V are the working matrices (global memory, or LDS in the _lds
+// variant); sh is 2560 doubles of LDS scratch.
+__device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict__ U, double* __restrict__ V,
+                              double* __restrict__ S, double* __restrict__ sh) {
   double* cs = sh;           // [512]
   double* sn = sh + 512;     // [512]
   int* pp = reinterpret_cast<int*>(sh + 1024);
@@ -319,10 +367,36 @@ __global__ void __launch_bounds__(1024) hestenes_kernel(double* __restrict__ A, 
   }
 }
 
+__global__ void __launch_bounds__(1024) hestenes_kernel(double* __restrict__ A, int m, double* __restrict__ U,
+                                                        double* __restrict__ V, double* __restrict__ S) {
+  extern __shared__ double sh[];
+  hestenes_body(A, m, U, V, S, sh);
+}
+
+// The same with A and V held in LDS (2 m^2 + 2560 doubles).
+__global__ void __launch_bounds__(1024) hestenes_lds_kernel(const double* __restrict__ Ag, int m,
+                                                            double* __restrict__ U, double* __restrict__ Vg,
+                                                            double* __restrict__ S) {
+  extern __shared__ double sh[];
+  double* A = sh + 2560;
+  double* V = A + m * m;
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) A[i] = Ag[i];
+  __syncthreads();
+  hestenes_body(A, m, U, V, S, sh);
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) Vg[i] = V[i];
+}
+
 static void hestenes(double* A, int m, double* U, double* V, double* S, hipStream_t st) {
   if (m > 1000) fail(TNB_EUNSUPPORTED, "SVD limited to 1000 x 1000");
   KTimer _t("svd_small", st, 0.0, 24.0 * m * m);
-  hipLaunchKernelGGL(hestenes_kernel, dim3(1), dim3(1024), 2560 * sizeof(double), st, A, m, U, V, S);
+  if (lds_fits(m)) {
+    const size_t shm = (2560 + 2 * size_t(m) * m) * sizeof(double);
+    allow_lds(hestenes_lds_kernel, shm);
+    hipLaunchKernelGGL(hestenes_lds_kernel, dim3(1), dim3(1024), shm, st, A, m, U, V, S);
+  } else {
+    hipLaunchKernelGGL(hestenes_kernel, dim3(1), dim3(1024), 2560 * sizeof(double), st, A, m, U, V, S);
+  }
   HIPC(hipGetLastError());
 }
 
