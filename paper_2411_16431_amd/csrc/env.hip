@@ -622,6 +622,137 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
   }
 }
 
+// Site diagram (K1) on the matrix cores, for Da, Db <= 16 and Dg <= 32.
+// Per cluster value x the diagram is a chain of two small products.  In the
+// 16x16x4 MFMA the result item v of lane l is row 4 v + l / 16, which is the
+// B operand row of k-step v: the first product's result feeds the second
+// without any data movement.
+//   apply : out[l] (Da x s)  = sum_{x in l} w(x) A[v'(x)] . (K[rho(x)] . Xt[u(x)])
+//   applyT: G[u]  (Dg x s)   = sum_{x in u} w(x) K[rho(x)]^T . (A[v'(x)]^T . Y[l(x)])
+// One wave per output block for apply (its x range is short); four waves
+// splitting the x range of an output block for applyT, summed through LDS.
+template <int NJ>
+__global__ void __launch_bounds__(64) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
+                                                      uint32_t Bup, uint32_t Bdn, const double* __restrict__ w,
+                                                      const double* __restrict__ A, int Da, int Db,
+                                                      const double* __restrict__ Kc, int Dg,
+                                                      const double* __restrict__ Xt, int s,
+                                                      double* __restrict__ out) {
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  const uint32_t l = blockIdx.x;
+  v4d acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int f = 0; f < nfree; ++f) {
+    const uint32_t x = pdep_dev(l, PL) | pdep_dev(uint32_t(f), FREE);
+    const double wx = w[x];
+    if (wx == 0.0) continue;
+    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;  // [b][g]
+    const double* Xu = Xt + size_t(pext_dev(x, Bup)) * Dg * s;  // [g][j]
+    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;  // [a][b]
+    v4d t[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) t[j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      if (4 * kk >= Dg) break;
+      const int g = 4 * kk + lk;
+      const double a = (li < Db && g < Dg) ? Kr[li * Dg + g] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int jj = 16 * j + li;
+        t[j] = mfma16(a, (g < Dg && jj < s) ? Xu[size_t(g) * s + jj] : 0.0, t[j]);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int b = 4 * kk + lk;
+      const double a = (li < Da && b < Db) ? wx * Av[li * Db + b] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[j] = mfma16(a, t[j][kk], acc[j]);
+    }
+  }
+  double* o = out + size_t(l) * Da * s;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 4 * v + lk, jj = 16 * j + li;
+      if (a < Da && jj < s) o[size_t(a) * s + jj] = acc[j][v];
+    }
+}
+
+template <int NJ>
+__global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL,
+                                                        uint32_t PR, uint32_t Bdn, const double* __restrict__ w,
+                                                        const double* __restrict__ A, int Da, int Db,
+                                                        const double* __restrict__ Kc, int Dg,
+                                                        const double* __restrict__ Y, int s,
+                                                        double* __restrict__ G) {
+  __shared__ double red[4][32][16 * NJ];
+  const int lane = threadIdx.x & 63, w4 = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const uint32_t u = blockIdx.x;
+  v4d acc[2][NJ];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[m][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int f = w4; f < nfree; f += 4) {
+    const uint32_t x = pdep_dev(u, Bup) | pdep_dev(uint32_t(f), FREE);
+    const double wx = w[x];
+    if (wx == 0.0) continue;
+    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;  // [b][g]
+    const double* Yl = Y + size_t(pext_dev(x, PL)) * Da * s;    // [a][j]
+    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;  // [a][b]
+    v4d t[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) t[j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {  // T (Db x s) = A^T (Db x Da) . Y (Da x s)
+      const int a = 4 * kk + lk;
+      const double av = (li < Db && a < Da) ? Av[a * Db + li] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int jj = 16 * j + li;
+        t[j] = mfma16(av, (a < Da && jj < s) ? Yl[size_t(a) * s + jj] : 0.0, t[j]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {  // G (Dg x s) += w K^T (Dg x Db) . T (Db x s)
+      if (16 * m >= Dg) break;
+      const int g = 16 * m + li;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int b = 4 * kk + lk;
+        const double kv = (g < Dg && b < Db) ? wx * Kr[b * Dg + g] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[m][j] = mfma16(kv, t[j][kk], acc[m][j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w4][16 * m + 4 * v + lk][16 * j + li] = acc[m][j][v];
+  __syncthreads();
+  double* o = G + size_t(u) * Dg * s;
+  for (int i = threadIdx.x; i < 32 * 16 * NJ; i += 256) {
+    const int g = i / (16 * NJ), jj = i % (16 * NJ);
+    if (g < Dg && jj < s) o[size_t(g) * s + jj] = red[0][g][jj] + red[1][g][jj] + red[2][g][jj] + red[3][g][jj];
+  }
+}
+
+#define TNB_SITE_LAUNCH(NJV, KERNEL, GRID, BLOCK, ST, ...)                                    \
+  switch (NJV) {                                                                             \
+    case 1: hipLaunchKernelGGL((KERNEL<1>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
+    case 2: hipLaunchKernelGGL((KERNEL<2>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
+    case 3: hipLaunchKernelGGL((KERNEL<3>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
+    case 4: hipLaunchKernelGGL((KERNEL<4>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
+    default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");                  \
+  }
+
 static size_t medf_bin_lds(int Kd, int nj) {
   const size_t Kp = size_t((Kd + 3) & ~3);
   size_t K2 = 1;
@@ -792,10 +923,15 @@ struct Zipper {
       KTimer _t("site_apply", st, 2.0 * s * Db * double(Dg + Da) * double(c.dL) * nfree,
                 8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
                        double(c.dL) * Da * s + double(c.dL) * nfree));
-      allow_big_lds(site_apply_kernel, size_t(Db) * s * sizeof(double));
-      hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
-                         k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
-                         conn.p, Dg, Xt, s, out);
+      if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
+        TNB_SITE_LAUNCH((s + 15) / 16, site_apply_mfma, dim3(c.dL), dim3(64), st, c.PL, FREE, nfree, c.PR, c.Bup,
+                        c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg, Xt, s, out);
+      } else {
+        allow_big_lds(site_apply_kernel, size_t(Db) * s * sizeof(double));
+        hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
+                           k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
+                           conn.p, Dg, Xt, s, out);
+      }
       HIPC(hipGetLastError());
         }
     } else {
@@ -860,10 +996,15 @@ struct Zipper {
       KTimer _t("site_applyT", st, 2.0 * s * Db * double(Dg + Da) * double(c.du) * nfree,
                 8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
                        double(c.dL) * Da * s + double(c.du) * nfree));
-      allow_big_lds(site_applyT_kernel, size_t(Db) * s * sizeof(double));
-      hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
-                         k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg,
-                         Yin, s, G);
+      if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
+        TNB_SITE_LAUNCH((s + 15) / 16, site_applyT_mfma, dim3(c.du), dim3(256), st, c.Bup, FREE, nfree, c.PL, c.PR,
+                        c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg, Yin, s, G);
+      } else {
+        allow_big_lds(site_applyT_kernel, size_t(Db) * s * sizeof(double));
+        hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
+                           k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg,
+                           Yin, s, G);
+      }
       HIPC(hipGetLastError());
         }
       // out[v] = sum_u W(v,u) G[u]
