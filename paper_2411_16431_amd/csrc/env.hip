@@ -415,35 +415,6 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
 // elements it feeds to the MFMA, so no LDS staging is needed for stage 1, and
 // the loads of the next item are issued as soon as the current item's stage 1
 // has consumed its registers, overlapping stage 2 and the barriers.
-template <int MODE>
-__device__ __forceinline__ void bin_item(const MedF& f, uint32_t rd, uint32_t b2, uint32_t chunk, int t, int li,
-                                         int nbins, const double* __restrict__ P, const double* __restrict__ Q,
-                                         int Da, int Db, int Kd, int s, const double** Pt, const double** Qt,
-                                         double* wgt) {
-  const RowGeom::Med& md = f.md;
-  const uint32_t free_bits = MODE == 0 ? (uint32_t(md.dL - 1) & ~md.pos_b2) : (uint32_t(md.dR - 1) & ~md.pos_d_rho);
-  const uint32_t fixed_bits = MODE == 0 ? pdep_dev(b2, md.pos_b2) : pdep_dev(rd, md.pos_d_rho);
-  const uint32_t item = fixed_bits | pdep_dev(uint32_t(t), free_bits);
-  *wgt = 0.0;
-  if (MODE == 0) {
-    const uint32_t l = item;
-    *Pt = P + size_t(l) * Db * Kd;
-    *Qt = Q + (size_t(pext_dev(l, md.pos_d_ell)) * md.drd + rd) * Kd * s;
-    if (li < nbins) {
-      const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(chunk * 16u + li, f.hR_pos);
-      *wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
-    }
-  } else {
-    const uint32_t rho = item;
-    *Pt = P + size_t(pext_dev(rho, md.pos_a2) + md.da2 * b2) * Da * Db;
-    *Qt = Q + size_t(rho) * Da * s;
-    if (li < nbins) {
-      const uint32_t l = pdep_dev(b2, md.pos_b2) | pdep_dev(chunk * 16u + li, f.hL_pos);
-      *wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
-    }
-  }
-}
-
 template <int MODE, int NJ>
 __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __restrict__ P,
                                                      const double* __restrict__ Q, int Da, int Db, int Kd, int s,
@@ -463,12 +434,60 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
   const int nkk = (Kd + 3) >> 2;
   const int b = b0 + li;
   const int j0 = blockIdx.z * 16 * NJ;  // first sketch column of this workgroup
+  // Item t of the class is fixed | pdep(t, free) (l for MODE 0, rho for MODE
+  // 1).  The fixed and free parts occupy disjoint bits, so every projection
+  // of the item is the OR of the projections of the two parts: the free
+  // parts are tabulated once per workgroup in LDS (classes of up to TMAX
+  // items), and the per-lane bin index of the weight is hoisted.
+  constexpr int TMAX = 1024;
+  __shared__ uint32_t tab_item[TMAX], tab_x[TMAX], tab_h[TMAX];
+  const uint32_t free_bits = MODE == 0 ? (uint32_t(md.dL - 1) & ~md.pos_b2) : (uint32_t(md.dR - 1) & ~md.pos_d_rho);
+  const uint32_t fixed = MODE == 0 ? pdep_dev(b2, md.pos_b2) : pdep_dev(rd, md.pos_d_rho);
+  const uint32_t xmask = MODE == 0 ? md.pos_d_ell : md.pos_a2;
+  const uint32_t hmask = MODE == 0 ? md.pos_h_ell : md.pos_h_rho;
+  const uint32_t fx = pext_dev(fixed, xmask), fh = pext_dev(fixed, hmask);
+  const bool tabbed = nitems <= TMAX;
+  if (tabbed) {
+    for (int t = threadIdx.x; t < nitems; t += blockDim.x) {
+      const uint32_t fr = pdep_dev(uint32_t(t), free_bits);
+      tab_item[t] = fr;
+      tab_x[t] = pext_dev(fr, xmask);
+      tab_h[t] = pext_dev(fr, hmask);
+    }
+    __syncthreads();
+  }
+  uint32_t lane_h = 0;  // the lane's bin, projected for the horizontal weight
+  if (li < nbins) {
+    if (MODE == 0)
+      lane_h = pext_dev(pdep_dev(rd, md.pos_d_rho) | pdep_dev(chunk * 16u + li, f.hR_pos), md.pos_h_rho);
+    else
+      lane_h = pext_dev(pdep_dev(b2, md.pos_b2) | pdep_dev(chunk * 16u + li, f.hL_pos), md.pos_h_ell);
+  }
   double pa[KK], qb[KK][NJ], wr = 0.0;
   auto fetch = [&](int t) {
     if (t >= nitems) return;
+    uint32_t item, xp, hp;
+    if (tabbed) {
+      item = fixed | tab_item[t];
+      xp = fx | tab_x[t];
+      hp = fh | tab_h[t];
+    } else {
+      const uint32_t fr = pdep_dev(uint32_t(t), free_bits);
+      item = fixed | fr;
+      xp = fx | pext_dev(fr, xmask);
+      hp = fh | pext_dev(fr, hmask);
+    }
     const double* Pt;
     const double* Qt;
-    bin_item<MODE>(f, rd, b2, chunk, t, li, nbins, P, Q, Da, Db, Kd, s, &Pt, &Qt, &wr);
+    if (MODE == 0) {  // item = l, xp = l_d(l), hp = h'(l)
+      Pt = P + size_t(item) * Db * Kd;
+      Qt = Q + (size_t(xp) * md.drd + rd) * Kd * s;
+      wr = li < nbins ? md.Wh[lane_h * md.Wh_sp + hp * md.Wh_sq] : 0.0;
+    } else {  // item = rho, xp = a'(rho), hp = h(rho)
+      Pt = P + size_t(xp + md.da2 * b2) * Da * Db;
+      Qt = Q + size_t(item) * Da * s;
+      wr = li < nbins ? md.Wh[hp * md.Wh_sp + lane_h * md.Wh_sq] : 0.0;
+    }
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
@@ -563,6 +582,22 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
     hR = pext_dev(rho, f.hR_pos);
     nitems = md.db2;
   }
+  // the class items' projections, tabulated once per workgroup (MODE 0; the
+  // fixed and free bits of l are disjoint, so projections split into an OR)
+  constexpr int TMAX = 1024;
+  __shared__ uint32_t tab_item[TMAX], tab_b[TMAX], tab_h[TMAX];
+  const bool tabbed = MODE == 0 && nitems <= TMAX;
+  const uint32_t fb = MODE == 0 ? pext_dev(fixed_bits, md.pos_b2) : 0u;
+  const uint32_t fhl = MODE == 0 ? pext_dev(fixed_bits, f.hL_pos) : 0u;
+  if (tabbed) {
+    for (int t = threadIdx.x; t < nitems; t += blockDim.x) {
+      const uint32_t fr = pdep_dev(uint32_t(t), free_bits);
+      tab_item[t] = fr;
+      tab_b[t] = pext_dev(fr, md.pos_b2);
+      tab_h[t] = pext_dev(fr, f.hL_pos);
+    }
+    __syncthreads();
+  }
   // two statically named register buffers (a runtime buffer index would put
   // the arrays in scratch memory)
   double pa0[KK], qb0[KK][NJ], pa1[KK], qb1[KK][NJ];
@@ -571,9 +606,19 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
     const double* Pt;
     const double* Qt;
     if (MODE == 0) {
-      const uint32_t l = fixed_bits | pdep_dev(uint32_t(t), free_bits);
+      uint32_t l, bp, hp;
+      if (tabbed) {
+        l = fixed_bits | tab_item[t];
+        bp = fb | tab_b[t];
+        hp = fhl | tab_h[t];
+      } else {
+        const uint32_t fr = pdep_dev(uint32_t(t), free_bits);
+        l = fixed_bits | fr;
+        bp = fb | pext_dev(fr, md.pos_b2);
+        hp = fhl | pext_dev(fr, f.hL_pos);
+      }
       Pt = P + size_t(l) * Db * rows;
-      Qt = Q + ((size_t(rd) * md.db2 + pext_dev(l, md.pos_b2)) * f.nHL + pext_dev(l, f.hL_pos)) * Db * s;
+      Qt = Q + ((size_t(rd) * md.db2 + bp) * f.nHL + hp) * Db * s;
     } else {
       Pt = P + size_t(a2 + md.da2 * uint32_t(t)) * rows * Db;
       Qt = Q + ((size_t(rd) * md.db2 + uint32_t(t)) * f.nHR + hR) * Db * s;
