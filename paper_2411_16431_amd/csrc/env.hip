@@ -426,14 +426,22 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nch = MODE == 0 ? f.chR : f.chL, nH = MODE == 0 ? f.nHR : f.nHL;
-  const uint32_t chunk = blockIdx.x % nch, pair = blockIdx.x / nch;
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so the
+  // njt sketch-column tiles of one output block are given ids i, i+8, ...:
+  // they run back to back on one XCD and share its L2 for the P operand.
+  const int njt = (s + 16 * NJ - 1) / (16 * NJ);
+  const uint32_t G = uint32_t(md.drd) * md.db2 * nch;
+  const uint32_t r8 = blockIdx.x >> 3;
+  const uint32_t g = (r8 / njt) * 8 + (blockIdx.x & 7);
+  if (g >= G) return;  // padding of the last group of 8
+  const uint32_t chunk = g % nch, pair = g / nch;
   const uint32_t rd = pair / md.db2, b2 = pair % md.db2;
   const int b0 = blockIdx.y * 16;
   const int nbins = min(16, nH - int(chunk) * 16);
   const int nitems = MODE == 0 ? md.dL / md.db2 : md.dR / md.drd;
   const int nkk = (Kd + 3) >> 2;
   const int b = b0 + li;
-  const int j0 = blockIdx.z * 16 * NJ;  // first sketch column of this workgroup
+  const int j0 = int(r8 % njt) * 16 * NJ;  // first sketch column of this workgroup
   // Item t of the class is fixed | pdep(t, free) (l for MODE 0, rho for MODE
   // 1).  The fixed and free parts occupy disjoint bits, so every projection
   // of the item is the OR of the projections of the two parts: the free
@@ -1002,8 +1010,9 @@ struct Zipper {
         if (Dg <= 32) {
           // one 16-column sketch tile per workgroup keeps the register count at
           // three waves per SIMD
-          hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16, nj), dim3(256), 0,
-                             st, f, conn.p, X2.p, Da, Db, Dg, s, Yf.p);
+          const unsigned G = unsigned(md.drd * md.db2 * f.chR);
+          hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0, st, f,
+                             conn.p, X2.p, Da, Db, Dg, s, Yf.p);
         } else {
           TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, conn.p,
                         X2.p, Da, Db, Dg, s, Yf.p);
@@ -1069,8 +1078,9 @@ struct Zipper {
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
                           double(md.drd) * md.db2 * f.nHL * Db * s));
         if (Da <= 32) {
-          hipLaunchKernelGGL((medf_bin_pipe<1, 1>), dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16, nj), dim3(256), 0,
-                             st, f, A.data.p, Yin, Da, Db, Da, s, Yf.p);
+          const unsigned G = unsigned(md.drd * md.db2 * f.chL);
+          hipLaunchKernelGGL((medf_bin_pipe<1, 1>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0, st, f,
+                             A.data.p, Yin, Da, Db, Da, s, Yf.p);
         } else {
           TNB_NJ_LAUNCH(nj, medf_bin_mfma, 1, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), shm, st, f, A.data.p,
                         Yin, Da, Db, Da, s, Yf.p);
