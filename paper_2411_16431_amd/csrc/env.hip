@@ -576,7 +576,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
   const int nkk = (Db + 3) >> 2;
   const int j0 = blockIdx.z * 16 * NJ;  // first sketch column of this workgroup
   int nitems;
-  uint32_t rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0;
+  uint32_t rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0, rho_blk = blockIdx.x;
   if (MODE == 0) {
     const uint32_t ld = blockIdx.x / md.drd;
     rd = blockIdx.x % md.drd;
@@ -584,10 +584,21 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
     fixed_bits = pdep_dev(ld, md.pos_d_ell);
     free_bits = uint32_t(md.dL - 1) & ~md.pos_d_ell;
   } else {
-    const uint32_t rho = blockIdx.x;
-    rd = pext_dev(rho, md.pos_d_rho);
-    a2 = pext_dev(rho, md.pos_a2);
-    hR = pext_dev(rho, f.hR_pos);
+    // XCD-aware order: the rho sharing (rho_d, hR) read the same Y2 slab;
+    // they get workgroup ids i, i+8, ... and so run back to back on one XCD
+    // (when their number is a multiple of 8; otherwise rho = blockIdx.x)
+    const uint32_t ng = uint32_t(md.drd) * f.nHR, nq = uint32_t(md.dR) / ng;
+    if (ng % 8 == 0) {
+      const uint32_t rest = uint32_t(md.dR - 1) & ~(md.pos_d_rho | f.hR_pos);
+      const uint32_t r8 = blockIdx.x >> 3, g = (r8 / nq) * 8 + (blockIdx.x & 7);
+      rd = g / f.nHR;
+      hR = g % f.nHR;
+      rho_blk = pdep_dev(rd, md.pos_d_rho) | pdep_dev(hR, f.hR_pos) | pdep_dev(r8 % nq, rest);
+    } else {
+      rd = pext_dev(rho_blk, md.pos_d_rho);
+      hR = pext_dev(rho_blk, f.hR_pos);
+    }
+    a2 = pext_dev(rho_blk, md.pos_a2);
     nitems = md.db2;
   }
   // the class items' projections, tabulated once per workgroup (MODE 0; the
@@ -666,7 +677,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[w][4 * v + lk][16 * j + li] = acc[j][v];
   __syncthreads();
-  double* o = out + size_t(blockIdx.x) * rows * s;
+  double* o = out + size_t(MODE == 0 ? blockIdx.x : rho_blk) * rows * s;
   (void)Dr2;
   for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
     const int r = i / (16 * NJ), jj = i % (16 * NJ);
