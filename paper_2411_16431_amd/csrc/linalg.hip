@@ -51,6 +51,69 @@ __global__ void gemm_finish_kernel(int nb, int M, int N, int nchunk, const doubl
   *dst = beta == 0.0 ? alpha * acc : alpha * acc + beta * *dst;
 }
 
+// Small output (M, N <= 64) over a long K chunk on the matrix cores: one
+// workgroup per (batch, chunk); wave w takes the k-steps of 4 that are w mod 4
+// in the chunk and accumulates the whole output in 16x16 MFMA tiles; the four
+// partial outputs are added in LDS in wave order, so the sum is deterministic.
+typedef double v4d_s __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) gemm_small_kernel(int M, int N, int64_t K, int64_t kchunk,
+                                                         const double* __restrict__ A, int64_t ars, int64_t acs,
+                                                         int64_t abs_, const double* __restrict__ B, int64_t brs,
+                                                         int64_t bcs, int64_t bbs, double* __restrict__ P,
+                                                         int64_t pbs_chunk, int64_t pbs_batch, int nb) {
+  __shared__ double red[64][65];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int b = int(blockIdx.y) % nb, chunk = int(blockIdx.y) / nb;
+  const int64_t k0 = int64_t(chunk) * kchunk;
+  const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+  const double* Ab = A + b * abs_;
+  const double* Bb = B + b * bbs;
+  const int mt = (M + 15) >> 4, nt = (N + 15) >> 4;
+  v4d_s acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d_s{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kb = k0 + 4 * w; kb < k1; kb += 16) {
+    const int64_t k = kb + lk;
+    const bool kok = k < k1;
+    double a[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * i + li;
+      a[i] = (i < mt && r < M && kok) ? Ab[r * ars + k * acs] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = 16 * j + li;
+      bv[j] = (j < nt && c < N && kok) ? Bb[k * brs + c * bcs] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < nt) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+  for (int src = 0; src < 4; ++src) {
+    if (w == src) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * i + 4 * v + lk, c = 16 * j + li;
+            red[r][c] = src == 0 ? acc[i][j][v] : red[r][c] + acc[i][j][v];
+          }
+    }
+    __syncthreads();
+  }
+  double* Pb = P + chunk * pbs_chunk + b * pbs_batch;
+  for (int i = threadIdx.x; i < M * N; i += blockDim.x) Pb[i] = red[i / N][i % N];
+}
+
 static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double* C, int64_t ldc,
                       int64_t bsc, double alpha, double beta, Scratch& ws, hipStream_t s) {
   const int64_t tiles2d = int64_t((M + TILE - 1) / TILE) * ((N + TILE - 1) / TILE);
@@ -70,8 +133,13 @@ static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double
   {
   KTimer _t("gemm", s, 2.0 * M * double(N) * double(K) * batch,
             8.0 * (double(M) * K + double(K) * N + double(M) * N) * batch);
-  hipLaunchKernelGGL(gemm_kernel, grid, dim3(TILE, TILE), 0, s, M, N, K, kchunk, A.p, A.rs, A.cs,
-                     A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
+  if (M <= 64 && N <= 64) {
+    hipLaunchKernelGGL(gemm_small_kernel, dim3(1, unsigned(batch * nchunk)), dim3(256), 0, s, M, N, K, kchunk, A.p,
+                       A.rs, A.cs, A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
+  } else {
+    hipLaunchKernelGGL(gemm_kernel, grid, dim3(TILE, TILE), 0, s, M, N, K, kchunk, A.p, A.rs, A.cs,
+                       A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
+  }
   HIPC(hipGetLastError());
   }
   const int64_t tot = per * batch;
