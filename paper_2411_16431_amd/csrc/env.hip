@@ -414,7 +414,9 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
 // 32, i.e. chi <= 16 for the new bond): each lane loads exactly the operand
 // elements it feeds to the MFMA, so no LDS staging is needed for stage 1, and
 // the loads of the next item are issued as soon as the current item's stage 1
-// has consumed its registers, overlapping stage 2 and the barriers.
+// has consumed its registers, overlapping stage 2 and the barriers.  Both
+// modes read P as [item][k][b] (16 consecutive b per load): MODE 1 gets the
+// MPS site as stored, MODE 0 a transposed copy of the connector, [l][g][b].
 template <int MODE, int NJ>
 __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __restrict__ P,
                                                      const double* __restrict__ Q, int Da, int Db, int Kd, int s,
@@ -487,7 +489,7 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
     }
     const double* Pt;
     const double* Qt;
-    if (MODE == 0) {  // item = l, xp = l_d(l), hp = h'(l)
+    if (MODE == 0) {  // item = l, xp = l_d(l), hp = h'(l); P = K transposed, [l][g][b]
       Pt = P + size_t(item) * Db * Kd;
       Qt = Q + (size_t(xp) * md.drd + rd) * Kd * s;
       wr = li < nbins ? md.Wh[lane_h * md.Wh_sp + hp * md.Wh_sq] : 0.0;
@@ -500,7 +502,7 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
     for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
       const bool ok = kk < nkk && k < Kd;
-      pa[kk] = (ok && b < Db) ? (MODE == 0 ? Pt[size_t(b) * Kd + k] : Pt[size_t(k) * Db + b]) : 0.0;
+      pa[kk] = (ok && b < Db) ? Pt[size_t(k) * Db + b] : 0.0;  // [k][b]: 16 consecutive b
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = j0 + 16 * j + li;
@@ -817,6 +819,17 @@ __global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t F
     default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");                  \
   }
 
+// out[n][c][r] = in[n][r][c] for n < count (per-item transpose of r x c blocks)
+__global__ void transpose_blocks_kernel(const double* __restrict__ in, int64_t count, int r, int c,
+                                        double* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= count * r * c) return;
+  const int64_t n = idx / (int64_t(r) * c);
+  const int rc = int(idx % (int64_t(r) * c));
+  const int i = rc / c, j = rc % c;
+  out[(n * c + j) * r + i] = in[idx];
+}
+
 static size_t medf_bin_lds(int Kd, int nj) {
   const size_t Kp = size_t((Kd + 3) & ~3);
   size_t K2 = 1;
@@ -932,7 +945,7 @@ struct Zipper {
   const tnb_env_opts& o;
   la::Scratch& ws;
   hipStream_t st;
-  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, SVT, Yf, Cin, Cout;
+  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, connT, SVT, Yf, Cin, Cout;
 
   // Widest sketch block whose diagram tiles fit the LDS and register budget.
   static int block_width(int Da, int Db, int Dg, int s) {
@@ -1021,9 +1034,14 @@ struct Zipper {
         if (Dg <= 32) {
           // one 16-column sketch tile per workgroup keeps the register count at
           // three waves per SIMD
+          // the kernel reads the connector as [l][g][b] (contiguous along b)
+          const int64_t nconn = int64_t(md.dL) * Db * Dg;
+          ensure(connT, size_t(nconn));
+          hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nconn)), dim3(256), 0, st, conn.p, int64_t(md.dL),
+                             Db, Dg, connT.p);
           const unsigned G = unsigned(md.drd * md.db2 * f.chR);
           hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0, st, f,
-                             conn.p, X2.p, Da, Db, Dg, s, Yf.p);
+                             connT.p, X2.p, Da, Db, Dg, s, Yf.p);
         } else {
           TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, conn.p,
                         X2.p, Da, Db, Dg, s, Yf.p);
