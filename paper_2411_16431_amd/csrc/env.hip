@@ -563,7 +563,9 @@ __global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __res
 }
 
 // medf_acc_mfma with the next item's operands prefetched into registers
-// (Db <= 32).
+// (Db <= 32).  P is read as [item][k][row] (16 consecutive rows per load):
+// MODE 0 gets the connector as stored ([l][b][g]), MODE 1 a transposed copy
+// of the MPS site ([sigma][b][a]).
 template <int MODE, int NJ>
 __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __restrict__ P,
                                                      const double* __restrict__ Q, int rows, int Db, int Dr2, int s,
@@ -648,7 +650,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
     for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
       const bool ok = kk < nkk && k < Db;
-      pa[kk] = (ok && row < rows) ? (MODE == 0 ? Pt[size_t(k) * rows + row] : Pt[size_t(row) * Db + k]) : 0.0;
+      pa[kk] = (ok && row < rows) ? Pt[size_t(k) * rows + row] : 0.0;  // [k][row]: 16 consecutive rows
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = j0 + 16 * j + li;
@@ -1053,8 +1055,13 @@ struct Zipper {
                    8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
                           double(md.dR) * Da * s));
         if (Db <= 32) {
-          // all sketch columns in one workgroup: the P operand is loaded once
-          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, A.data.p, Yf.p, Da, Db, 0, s,
+          // all sketch columns in one workgroup: the P operand is loaded once;
+          // it reads the MPS site transposed, [sigma][b][a]
+          const int64_t nsite = int64_t(A.size());
+          ensure(connT, size_t(nsite));
+          hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nsite)), dim3(256), 0, st, A.data.p,
+                             int64_t(A.d), Da, Db, connT.p);
+          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, connT.p, Yf.p, Da, Db, 0, s,
                         out);
         } else {
           TNB_NJ_LAUNCH(nj, medf_acc_mfma, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, A.data.p, Yf.p, Da, Db, 0, s,
