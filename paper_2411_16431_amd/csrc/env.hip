@@ -581,9 +581,19 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
   const int j0 = blockIdx.z * 16 * NJ;  // first sketch column of this workgroup
   int nitems;
   uint32_t rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0, rho_blk = blockIdx.x;
+  uint32_t ld = 0;
   if (MODE == 0) {
-    const uint32_t ld = blockIdx.x / md.drd;
-    rd = blockIdx.x % md.drd;
+    // XCD-aware order (when d_rho_d is a multiple of 8): the blocks of one
+    // rho_d read the same W2 slab; they get workgroup ids i, i+8, ... and run
+    // back to back on one XCD
+    if (md.drd % 8 == 0) {
+      const uint32_t r8 = blockIdx.x >> 3;
+      ld = r8 % md.dld;
+      rd = (r8 / md.dld) * 8 + (blockIdx.x & 7);
+    } else {
+      ld = blockIdx.x / md.drd;
+      rd = blockIdx.x % md.drd;
+    }
     nitems = md.dL / md.dld;
     fixed_bits = pdep_dev(ld, md.pos_d_ell);
     free_bits = uint32_t(md.dL - 1) & ~md.pos_d_ell;
@@ -681,7 +691,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[w][4 * v + lk][16 * j + li] = acc[j][v];
   __syncthreads();
-  double* o = out + size_t(MODE == 0 ? blockIdx.x : rho_blk) * rows * s;
+  double* o = out + size_t(MODE == 0 ? ld * md.drd + rd : rho_blk) * rows * s;
   (void)Dr2;
   for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
     const int r = i / (16 * NJ), jj = i % (16 * NJ);
