@@ -354,20 +354,35 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
   for (int sweep = 0; sweep < 60; ++sweep) {
     double worst = 0.0;
     for (int round = 0; round < mm - 1; ++round) {
-      for (int a = tid; a < mm / 2; a += nt) {
-        int p1 = (a == 0) ? 0 : 1 + (a - 1 + round) % (mm - 1);
-        int p2 = 1 + (mm - 2 - a + round) % (mm - 1);
-        int p = p1 < p2 ? p1 : p2, q = p1 < p2 ? p2 : p1;
-        double c = 1.0, sv = 0.0;
-        if (q < m) {
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = 0; i < m; ++i) {
+      // 16 lanes per column pair: strided partial dot products, then a
+      // butterfly over the 16 lanes (the same order on every lane)
+      const int sub = tid & 15;
+      for (int a0 = tid >> 4; a0 < (mm / 2 + 15) / 16 * 16; a0 += nt >> 4) {
+        const int a = a0;
+        const bool act = a < mm / 2;
+        int p = 0, q = m;
+        if (act) {
+          const int p1 = (a == 0) ? 0 : 1 + (a - 1 + round) % (mm - 1);
+          const int p2 = 1 + (mm - 2 - a + round) % (mm - 1);
+          p = p1 < p2 ? p1 : p2;
+          q = p1 < p2 ? p2 : p1;
+        }
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (act && q < m)
+          for (int i = sub; i < m; i += 16) {
             const double x = A[i * m + p], y = A[i * m + q];
             al = fma(x, x, al);
             be = fma(y, y, be);
             ga = fma(x, y, ga);
           }
-          if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        for (int o = 8; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 16);
+          be += __shfl_xor(be, o, 16);
+          ga += __shfl_xor(ga, o, 16);
+        }
+        if (act && sub == 0) {
+          double c = 1.0, sv = 0.0;
+          if (q < m && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -375,11 +390,11 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
             const double r = fabs(ga) / sqrt(al * be);
             worst = fmax(worst, r);
           }
+          pp[a] = p;
+          qq[a] = q;
+          cs[a] = c;
+          sn[a] = sv;
         }
-        pp[a] = p;
-        qq[a] = q;
-        cs[a] = c;
-        sn[a] = sv;
       }
       __syncthreads();
       for (int idx = tid; idx < (mm / 2) * m; idx += nt) {
