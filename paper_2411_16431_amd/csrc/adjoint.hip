@@ -75,6 +75,67 @@ __global__ void adj_q_kernel(BCol c, const int32_t* __restrict__ X, int ncell, c
   q[idx] = g * acc;
 }
 
+// adj_q on the matrix cores (Dl, Dr <= 16): one wave per cluster value x.
+// For the parents in tiles of 16, Y = V'_x (16 x Dl) . A2c[v'(x)] (Dl x Dr)
+// runs on v_mfma_f64_16x16x4f64; lane l then holds Y[b][e] with e = l % 16,
+// multiplies it by R[b][e][pi(x)] (RT: R transposed to [anc][pi][e]) and the
+// 16 lanes of one row sum over e with a fixed butterfly.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) adj_q_mfma(BCol c, const int32_t* __restrict__ X, int ncell,
+                                                  const double* __restrict__ Vp, const double* __restrict__ A2c,
+                                                  int Dl, int Dr, const double* __restrict__ RT,
+                                                  const int32_t* __restrict__ rid, int nb, double* __restrict__ q) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int64_t d = int64_t(1) << c.k;
+  const int64_t xw = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (xw >= d) return;  // x is uniform over the wave
+  const uint32_t x = uint32_t(xw);
+  const uint32_t xh = pext_dev(x, c.Bxh), bd = pext_dev(x, c.Bbd), pi = pext_dev(x, c.PRR);
+  const double w0 = wloc(c, x);
+  const double* Av = A2c + size_t(pext_dev(x, c.Bvd)) * Dl * Dr;
+  double bv[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int m = 4 * kk + lk;
+    bv[kk] = (m < Dl && li < Dr) ? Av[m * Dr + li] : 0.0;
+  }
+  const int64_t vstride = int64_t(c.dxh) * c.dbd * Dl;
+  const double* Vx = Vp + (size_t(xh) * c.dbd + bd) * Dl;
+  for (int b0 = 0; b0 < nb; b0 += 16) {
+    v4d y = v4d{0.0, 0.0, 0.0, 0.0};
+    const int b = b0 + li;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int m = 4 * kk + lk;
+      const double a = (b < nb && m < Dl) ? Vx[b * vstride + m] : 0.0;
+      y = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[kk], y, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int bb = b0 + 4 * v + lk;  // row of item v; column e = li
+      double t = 0.0;
+      if (bb < nb && li < Dr) t = y[v] * RT[(size_t(rid[bb]) * c.dpi + pi) * Dr + li];
+      for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 16);
+      if (li == 0 && bb < nb) {
+        const double g = w0 == 0.0 ? 0.0 : w0 * phi_of(c, X + size_t(bb) * ncell, x);
+        q[size_t(bb) * d + x] = g * t;
+      }
+    }
+  }
+}
+
+// out[a][j][i] = in[a][i][j] for a < count (per-item transpose of r x c blocks)
+__global__ void adj_transpose_kernel(const double* __restrict__ in, int64_t count, int r, int c,
+                                     double* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= count * r * c) return;
+  const int64_t n = idx / (int64_t(r) * c);
+  const int64_t rc = idx % (int64_t(r) * c);
+  const int64_t i = rc / c, j = rc % c;
+  out[(n * c + j) * r + i] = in[idx];
+}
+
 // Lambda'[b][e][pi] = sum_{x: pi(x) = pi} w phi_b(x) (V'[b][xh(x)][b'(x)] . A2c[v'(x)])[e]
 __global__ void adj_lam_kernel(BCol c, const int32_t* __restrict__ X, int ncell, const double* __restrict__ Vp,
                                const double* __restrict__ A2c, int Dl, int Dr, int nb, double* __restrict__ Lam) {
@@ -347,8 +408,18 @@ extern "C" tnb_status tnb_row_moments(tnb_beam* bm, double* d_m1, int64_t m1_len
         {
           KTimer _t("adj_q", st, double(nb) * dn * (2.0 * An.dl * An.dr + 2.0 * An.dr),
                     8.0 * (double(nb) * dn + An.size() + double(bm->nanc) * An.dr * gn.dpi));
-          hipLaunchKernelGGL(adj_q_kernel, dim3(nblk(int64_t(nb) * dn)), dim3(256), 0, st, gn, bm->X.p, bm->ncell,
-                             bm->vp.p, An.data.p, An.dl, An.dr, bm->R[cn].p, bm->rid.p, nb, bm->qa.p);
+          if (An.dl <= 16 && An.dr <= 16) {
+            // R^{(c')} transposed to [anc][pi][e] for the e-contiguous reads of adj_q_mfma
+            const int64_t nr = int64_t(bm->nanc) * An.dr * gn.dpi;
+            ensure(bm->rt0, size_t(nr));
+            hipLaunchKernelGGL(adj_transpose_kernel, dim3(nblk(nr)), dim3(256), 0, st, bm->R[cn].p,
+                               int64_t(bm->nanc), An.dr, gn.dpi, bm->rt0.p);
+            hipLaunchKernelGGL(adj_q_mfma, dim3(unsigned((dn + 3) / 4)), dim3(256), 0, st, gn, bm->X.p, bm->ncell,
+                               bm->vp.p, An.data.p, An.dl, An.dr, bm->rt0.p, bm->rid.p, nb, bm->qa.p);
+          } else {
+            hipLaunchKernelGGL(adj_q_kernel, dim3(nblk(int64_t(nb) * dn)), dim3(256), 0, st, gn, bm->X.p,
+                               bm->ncell, bm->vp.p, An.data.p, An.dl, An.dr, bm->R[cn].p, bm->rid.p, nb, bm->qa.p);
+          }
         }
         HIPC(hipGetLastError());
         moments_of(bm, bm->qa.p, dn, cn - c, d_m1, d_m2, st);
