@@ -125,6 +125,52 @@ __global__ void __launch_bounds__(256) adj_q_mfma(BCol c, const int32_t* __restr
   }
 }
 
+// Lambda' on the matrix cores (Dl, Dr <= 16): one wave per pi, summing over
+// the cluster values x of the class; Y = V'_x A2c[v'(x)] for 16 parents per
+// MFMA tile, weighted by w phi_b(x), written [b][pi][e] (e along the lanes).
+__global__ void __launch_bounds__(256) adj_lam_mfma(BCol c, const int32_t* __restrict__ X, int ncell,
+                                                    const double* __restrict__ Vp, const double* __restrict__ A2c,
+                                                    int Dl, int Dr, int nb, double* __restrict__ LamT) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int64_t pw = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (pw >= c.dpi) return;  // pi is uniform over the wave
+  const uint32_t pi = uint32_t(pw);
+  const uint32_t full = c.k ? ((1u << c.k) - 1u) : 0u;
+  const uint32_t FREE = full & ~c.PRR;
+  const int nf = 1 << __builtin_popcount(FREE);
+  const uint32_t base = pdep_dev(pi, c.PRR);
+  const int64_t vstride = int64_t(c.dxh) * c.dbd * Dl;
+  for (int b0 = 0; b0 < nb; b0 += 16) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int b = b0 + li;
+    for (int f = 0; f < nf; ++f) {
+      const uint32_t x = base | pdep_dev(uint32_t(f), FREE);
+      const double w0 = wloc(c, x);
+      if (w0 == 0.0) continue;
+      const double* Av = A2c + size_t(pext_dev(x, c.Bvd)) * Dl * Dr;
+      const double* Vx = Vp + (size_t(pext_dev(x, c.Bxh)) * c.dbd + pext_dev(x, c.Bbd)) * Dl;
+      v4d y = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int m = 4 * kk + lk;
+        const double a = (b < nb && m < Dl) ? Vx[b * vstride + m] : 0.0;
+        const double bvv = (m < Dl && li < Dr) ? Av[m * Dr + li] : 0.0;
+        y = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bvv, y, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int bb = b0 + 4 * v + lk;
+        if (bb < nb) acc[v] = fma(w0 * phi_of(c, X + size_t(bb) * ncell, x), y[v], acc[v]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int bb = b0 + 4 * v + lk;
+      if (bb < nb && li < Dr) LamT[(size_t(bb) * c.dpi + pi) * Dr + li] = acc[v];
+    }
+  }
+}
+
 // out[a][j][i] = in[a][i][j] for a < count (per-item transpose of r x c blocks)
 __global__ void adj_transpose_kernel(const double* __restrict__ in, int64_t count, int r, int c,
                                      double* __restrict__ out) {
@@ -136,7 +182,8 @@ __global__ void adj_transpose_kernel(const double* __restrict__ in, int64_t coun
   out[(n * c + j) * r + i] = in[idx];
 }
 
-// Lambda'[b][e][pi] = sum_{x: pi(x) = pi} w phi_b(x) (V'[b][xh(x)][b'(x)] . A2c[v'(x)])[e]
+// Lambda'[b][e][pi] = sum_{x: pi(x) = pi} w phi_b(x) (V'[b][xh(x)][b'(x)] . A2c[v'(x)])[e],
+// stored [b][pi][e]
 __global__ void adj_lam_kernel(BCol c, const int32_t* __restrict__ X, int ncell, const double* __restrict__ Vp,
                                const double* __restrict__ A2c, int Dl, int Dr, int nb, double* __restrict__ Lam) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -161,11 +208,11 @@ __global__ void adj_lam_kernel(BCol c, const int32_t* __restrict__ X, int ncell,
     for (int m = 0; m < Dl; ++m) v = fma(Vb[m], Av[size_t(m) * Dr], v);
     acc = fma(g, v, acc);
   }
-  Lam[idx] = acc;
+  Lam[(size_t(b) * c.dpi + pi) * Dr + e] = acc;  // [b][pi][e]
 }
 
 // Lh[b][xh][a'][be] = sum_{pi: a'(pi) = a'} Lambda[b][be][pi] W_h(h(pi), xh)
-// (c: geometry of column c'; pi runs over PRR of column c'-1)
+// (c: geometry of column c'; pi runs over PRR of column c'-1; Lambda stored [b][pi][be])
 __global__ void adj_lh_kernel(BCol c, int dpi_prev, const double* __restrict__ Lam, int nb, int Dl,
                               double* __restrict__ Lh) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -178,11 +225,11 @@ __global__ void adj_lh_kernel(BCol c, int dpi_prev, const double* __restrict__ L
   const uint32_t FREEh = c.pos_h & ~c.pos_a;
   const int nf = 1 << __builtin_popcount(FREEh);
   const uint32_t base = pdep_dev(a2, c.pos_a);
-  const double* Lb = Lam + (size_t(b) * Dl + be) * dpi_prev;
+  const double* Lb = Lam + size_t(b) * dpi_prev * Dl + be;  // Lambda stored [b][pi][be]
   double acc = 0.0;
   for (int f = 0; f < nf; ++f) {
     const uint32_t pi = base | pdep_dev(uint32_t(f), FREEh);
-    acc = fma(Lb[pi], c.Wh[pext_dev(pi, c.pos_h) * c.Wh_sp + xh * c.Wh_sq], acc);
+    acc = fma(Lb[size_t(pi) * Dl], c.Wh[pext_dev(pi, c.pos_h) * c.Wh_sp + xh * c.Wh_sq], acc);
   }
   Lh[idx] = acc;
 }
@@ -376,8 +423,13 @@ extern "C" tnb_status tnb_row_moments(tnb_beam* bm, double* d_m1, int64_t m1_len
         {
           KTimer _t("adj_lam", st, 2.0 * nb * double(int64_t(1) << gc.k) * Ac.dl * Ac.dr,
                     8.0 * (double(nb) * Ac.dr * gc.dpi + double(nb) * gc.dxh * gc.dbd * Ac.dl + Ac.size()));
-          hipLaunchKernelGGL(adj_lam_kernel, dim3(nblk(int64_t(nb) * Ac.dr * gc.dpi)), dim3(256), 0, st, gc, bm->X.p,
-                             bm->ncell, bm->vp.p, Ac.data.p, Ac.dl, Ac.dr, nb, bm->lam.p);
+          if (Ac.dl <= 16 && Ac.dr <= 16) {
+            hipLaunchKernelGGL(adj_lam_mfma, dim3(unsigned((gc.dpi + 3) / 4)), dim3(256), 0, st, gc, bm->X.p,
+                               bm->ncell, bm->vp.p, Ac.data.p, Ac.dl, Ac.dr, nb, bm->lam.p);
+          } else {
+            hipLaunchKernelGGL(adj_lam_kernel, dim3(nblk(int64_t(nb) * Ac.dr * gc.dpi)), dim3(256), 0, st, gc,
+                               bm->X.p, bm->ncell, bm->vp.p, Ac.data.p, Ac.dl, Ac.dr, nb, bm->lam.p);
+          }
         }
         normalise_rows(bm->lam.p, int64_t(Ac.dr) * gc.dpi, nb, nullptr, st);
         // next column
