@@ -140,8 +140,10 @@ tnb_status tnb_marginals(tnb_beam* beam, double* d_out, int64_t out_len, tnb_str
 /* One branch-and-bound step (Fig. 3): branch every parent over all d values
  * of the next cluster, score with the chain rule (Eq. 7) in log space, keep
  * the most probable candidate of every boundary configuration (Eq. 8; ties
- * go to the smaller (parent, x)), then the M most probable.  At the last
- * cluster no merge is done.  p_disc_log (host, may be NULL) receives the log
+ * go to the smaller (parent, x)), then the M most probable.  When no fixed
+ * cluster couples to an unfixed one (at the last cluster, or when only
+ * uncoupled clusters remain) no merge is done.  p_disc_log (host, may be
+ * NULL) receives the log
  * of the largest probability discarded so far (-inf if none).
  * TNB_EINVAL when every cluster is already fixed. */
 tnb_status tnb_branch_step(tnb_beam* beam, double* p_disc_log, tnb_stream stream);

@@ -147,7 +147,6 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
         rid = np.arange(X.shape[0])
         for c in range(C):
             n = r * C + c
-            last = (n == ncell - 1)
             q, vec = marginals(net, env, r, c, X, L, Rrow[c][rid])
             # Eq. (9) is a ratio of two contractions of the same network, so a
             # common sign of the approximate environment cancels: entries are
@@ -166,8 +165,11 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
             bb, xx, sc = bb.ravel(), xx.ravel(), score.ravel()
             ok = np.isfinite(sc)
             bb, xx, sc = bb[ok], xx[ok], sc[ok]
-            if merge and not last:
-                masks = boundary_key_masks(net, n + 1)
+            # merge by boundary (Eq. 8) while some fixed cluster still couples
+            # to an unfixed one; with an empty boundary (the last step, or only
+            # uncoupled clusters left) every candidate is kept (R12)
+            masks = boundary_key_masks(net, n + 1)
+            if merge and masks:
                 keycols = []
                 for (k, U) in masks:
                     vals = xx if k == n else X[bb, k]

@@ -288,7 +288,7 @@ __global__ void group_kernel(const double* __restrict__ score, int k, uint32_t U
     }
   } else if (idx < nb * d) {
     const double s = score[idx];
-    // no merge (last cluster): every candidate is its own group
+    // no merge (empty boundary): every candidate is its own group
     if (s > -INFINITY) cnd = Cand{uint64_t(idx), score_key(s), uint32_t(idx / d), uint32_t(idx % d)};
   }
   out[idx] = cnd;
@@ -648,7 +648,6 @@ extern "C" tnb_status tnb_branch_step(tnb_beam* bm, double* p_disc_log, tnb_stre
     const int nb = bm->npar;
     const int k = L.k[n];
     const int64_t d = int64_t(1) << k;
-    const bool last = n == bm->ncell - 1;
     compute_q(bm, st);
     ensure(bm->score, size_t(nb) * d);
     HIPC(hipMemsetAsync(bm->dead.p, 0, sizeof(int), st));
@@ -669,6 +668,10 @@ extern "C" tnb_status tnb_branch_step(tnb_beam* bm, double* p_disc_log, tnb_stre
       if (kk == n) Un = U;
       else if (U) { kcells.push_back(kk); kmasks.push_back(U); }
     }
+    // merge by boundary (Eq. 8) while some fixed cluster still couples to an
+    // unfixed one; with an empty boundary (the last cluster, or only
+    // uncoupled clusters left) every candidate is its own group
+    const bool last = Un == 0 && kmasks.empty();
     int totbits = 0;
     for (auto m : kmasks) totbits += popcount32(m);
     const int W = std::max(1, (totbits + 31) / 32);

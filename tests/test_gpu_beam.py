@@ -103,3 +103,40 @@ def test_marginals_sum_to_one():
         p = beam.marginals().cpu().numpy()
         assert np.allclose(p.sum(axis=1), 1.0, atol=1e-12) and (p >= 0).all()
         beam.step()
+
+
+def test_bench_workload_properties():
+    # the full bench workload (Zephyr Z_2, t=4, chi=16, M=64): every returned
+    # state is a valid spin vector whose energy the oracle recomputes bit for
+    # bit, energies ascend, and the marginals of the first steps are
+    # probability vectors
+    pk, torch = _gpu()
+    import bench
+    wl = bench.WORKLOADS["zephyr_z2_t4_plain"]
+    inst = bench.make(wl)
+    res = pk.solve(inst, wl["beta"], chi=wl["chi"], M=wl["M"], K=wl["K"], power_iters=2, seed=4242)
+    S = res["states"]
+    assert S.shape == (wl["K"], inst.n_spins) and np.all(np.abs(S) == 1)
+    assert len({s.tobytes() for s in S}) == len(S)
+    assert np.all(np.diff(res["energies"]) >= 0)
+    assert np.array_equal(res["energies"], ising.energies(inst, S))
+    assert res["energies"][0] >= -(np.abs(inst.J).sum() + np.abs(inst.h).sum())
+    assert np.isfinite(res["logZ"])
+    beam = pk.Beam(res["env"], wl["M"])
+    for _ in range(3):
+        p = beam.marginals().cpu().numpy()
+        assert np.allclose(p.sum(axis=1), 1.0, atol=1e-12) and (p >= 0).all()
+        beam.step()
+
+
+def test_planted_zephyr_z2_t4_full_size():
+    # planted loops at the bench's lattice size, chi and beam: the exact ground
+    # energy E0 is the sum of the loop minima.  The heuristic need not reach it
+    # at chi = 16 (this instance ends 5 above it), but no returned state may lie
+    # below it, and every returned energy is the oracle's, bit for bit
+    pk, torch = _gpu()
+    inst, s, E0 = planted_loops(2, 4, 91, loops_per_cell=2)
+    res = pk.solve(inst, 1.0, chi=16, M=64, K=4)
+    assert np.array_equal(res["energies"], ising.energies(inst, res["states"]))
+    assert res["energies"][0] >= E0 - 1e-9
+    assert ising.energies(inst, s[None, :].astype(np.int8))[0] == E0
