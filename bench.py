@@ -154,6 +154,22 @@ def adjoint_compare(pk, torch, env, wl, inst):
             "max_abs_diff_adjoint_vs_per_branch": float((m1 - pb).abs().max().item())}
 
 
+def planted_gap(pk, wl, env_kw):
+    """Energy gap d_E = (E - E0) / (2 |E0|) (Eq. 14) on a planted instance of
+    the same lattice, chi and beam, whose exact ground energy E0 is the sum of
+    its loop minima: the oracle cannot solve the random workload at t = 4, so
+    this is the stand-in for the gap against an exact reference."""
+    if wl["kind"] != "zephyr":
+        return None
+    from tnb_inputs import planted_loops
+    m, t = wl["kw"]["m"], wl["kw"]["t"]
+    inst, _, E0 = planted_loops(m, t, 91, loops_per_cell=2)
+    res = pk.solve(inst, wl["beta"], chi=wl["chi"], M=wl["M"], K=1, **env_kw)
+    E = float(res["energies"][0])
+    return {"instance": "planted loops, Zephyr Z_%d t=%d, seed 91, 2 loops per cell" % (m, t),
+            "E0_exact": float(E0), "best_energy": E, "d_E": (E - E0) / (2 * abs(E0))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -208,6 +224,7 @@ def main():
               "med": (prof.get("med_apply", (0, 0))[1] + prof.get("med_applyT", (0, 0))[1]
                       + prof.get("medf_Y2", (0, 0))[1] + prof.get("medf_W2", (0, 0))[1]) / args.steps}
     adj = adjoint_compare(pk, torch, res["env"], wl, inst)
+    planted = planted_gap(pk, wl, env_kw)
     print("adjoint comparison done", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
@@ -221,7 +238,7 @@ def main():
                    "lattice": [int(inst.R), int(inst.C)], "beta": wl["beta"], "chi": wl["chi"],
                    "beam_M": wl["M"], "returned_K": wl["K"], "mode": "plain (per-step marginals, no adjoint)",
                    "power_iters": args.power_iters},
-        "best_energy": float(res["energies"][0]), "energy_gap_vs_oracle": None,
+        "best_energy": float(res["energies"][0]), "energy_gap_vs_oracle": None, "energy_gap_planted": planted,
         "logZ": res["logZ"], "spin_marginals_per_step": marg,
         "roofline": roof, "cpu_baseline": cpu, "adjoint": adj,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
