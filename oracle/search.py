@@ -16,10 +16,6 @@ from .bmps import sub, _segment_sum
 from .ising import energies
 
 
-class RowEnv:
-    """Right environments R^{(c)}[beta, pi_c] of row r for one parent."""
-
-
 def _row_data(net, env, r):
     C = net.C
     psi = env.psi[r + 1]
