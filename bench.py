@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--workload", default="zephyr_z2_t4_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--power-iters", type=int, default=2)
+    ap.add_argument("--no-planted", action="store_true",
+                    help="skip the planted-instance energy gap (profiling runs: keeps rocprof's kernel averages to the timed workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 1 GiB device copy, the reference dispatch for HBM byte counters")
     return ap.parse_args()
@@ -224,7 +226,7 @@ def main():
               "med": (prof.get("med_apply", (0, 0))[1] + prof.get("med_applyT", (0, 0))[1]
                       + prof.get("medf_Y2", (0, 0))[1] + prof.get("medf_W2", (0, 0))[1]) / args.steps}
     adj = adjoint_compare(pk, torch, res["env"], wl, inst)
-    planted = planted_gap(pk, wl, env_kw)
+    planted = None if args.no_planted else planted_gap(pk, wl, env_kw)
     print("adjoint comparison done", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
