@@ -61,13 +61,56 @@ __global__ void bitonic_step(Cand* __restrict__ a, int64_t n, int64_t j, int64_t
 }
 
 
+// All stages with j < kChunk run inside one workgroup on a kChunk-element
+// slice held in LDS: the first kernel performs every stage of k <= kChunk,
+// the second the j < kChunk stages of one larger k.  The compare-exchange
+// network is the same as the one-launch-per-stage version, so the result is
+// identical.
+constexpr int kChunk = 2048;
+
+__global__ void __launch_bounds__(1024) bitonic_local(Cand* __restrict__ a, int64_t n, int64_t kfix) {
+  __shared__ Cand sh[kChunk];
+  const int64_t base = int64_t(blockIdx.x) * kChunk;
+  for (int i = threadIdx.x; i < kChunk; i += blockDim.x) sh[i] = a[base + i];
+  __syncthreads();
+  const int64_t k0 = kfix ? kfix : 2, k1 = kfix ? kfix : kChunk;
+  for (int64_t k = k0; k <= k1; k <<= 1) {
+    for (int64_t j = (kfix ? kChunk : k) >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < kChunk / 2; t += blockDim.x) {
+        const int i = int(2 * j * (t / j) + (t % j));  // lower element of the pair
+        const int l = i + int(j);
+        const bool up = ((base + i) & k) == 0;
+        const Cand x = sh[i], y = sh[l];
+        if (up ? cand_less(y, x) : cand_less(x, y)) {
+          sh[i] = y;
+          sh[l] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < kChunk; i += blockDim.x) a[base + i] = sh[i];
+  (void)n;
+}
+
 static void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st) {
   int lg = 0;
   while ((int64_t(1) << lg) < npow2) ++lg;
   KTimer _t("sort", st, 0.0, 2.0 * sizeof(Cand) * double(npow2) * lg * (lg + 1) / 2);
-  for (int64_t k = 2; k <= npow2; k <<= 1)
-    for (int64_t j = k >> 1; j > 0; j >>= 1)
+  if (npow2 < kChunk) {
+    for (int64_t k = 2; k <= npow2; k <<= 1)
+      for (int64_t j = k >> 1; j > 0; j >>= 1)
+        hipLaunchKernelGGL(bitonic_step, dim3(nblk(npow2)), dim3(256), 0, st, a, npow2, j, k);
+    HIPC(hipGetLastError());
+    return;
+  }
+  const unsigned nchunk = unsigned(npow2 / kChunk);
+  hipLaunchKernelGGL(bitonic_local, dim3(nchunk), dim3(1024), 0, st, a, npow2, int64_t(0));
+  for (int64_t k = 2 * kChunk; k <= npow2; k <<= 1) {
+    for (int64_t j = k >> 1; j >= kChunk; j >>= 1)
       hipLaunchKernelGGL(bitonic_step, dim3(nblk(npow2)), dim3(256), 0, st, a, npow2, j, k);
+    hipLaunchKernelGGL(bitonic_local, dim3(nchunk), dim3(1024), 0, st, a, npow2, k);
+  }
   HIPC(hipGetLastError());
 }
 
