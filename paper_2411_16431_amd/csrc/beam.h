@@ -64,7 +64,7 @@ struct tnb_beam {
   tnb::DevBuf<double> q, score, T, u, U, V;
   tnb::DevBuf<tnb::Cand> cand, win;
   tnb::DevBuf<int> flag, dead;
-  tnb::DevBuf<int64_t> pos, total;
+  tnb::DevBuf<int64_t> pos, total, tsum;
   tnb::DevBuf<uint32_t> words, cls, km;
   tnb::DevBuf<int> kc;
   tnb::DevBuf<int32_t> cell_of, bit;

@@ -345,13 +345,36 @@ __global__ void winner_flag_kernel(const Cand* __restrict__ a, int64_t n, int* _
 }
 
 // exclusive scan of flags in one block (n up to a few million: chunked loop)
-__global__ void scan_kernel(const int* __restrict__ flag, int64_t n, int64_t* __restrict__ pos, int64_t* __restrict__ total) {
+// Exclusive scan of 0/1 flags in three launches: tile sums (tiles of
+// kScanTile flags, read coalesced), a scan of the tile sums in one
+// workgroup, then each tile's scan with its offset.  Integer arithmetic, so
+// the result does not depend on the decomposition.
+constexpr int kScanTile = 4096;
+
+__global__ void __launch_bounds__(256) scan_tiles_kernel(const int* __restrict__ flag, int64_t n,
+                                                         int64_t* __restrict__ tsum) {
+  __shared__ int64_t red[256];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  int64_t s = 0;
+  for (int i = threadIdx.x; i < kScanTile; i += 256)
+    if (base + i < n) s += flag[base + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tsum[blockIdx.x] = red[0];
+}
+
+__global__ void scan_kernel(const int64_t* __restrict__ x, int64_t n, int64_t* __restrict__ pos,
+                            int64_t* __restrict__ total) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int64_t chunk = (n + nt - 1) / nt;
   const int64_t lo = t * chunk, hi = lo + chunk < n ? lo + chunk : n;
   int64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += flag[i];
+  for (int64_t i = lo; i < hi; ++i) s += x[i];
   part[t] = s;
   __syncthreads();
   if (t == 0) {
@@ -361,7 +384,38 @@ __global__ void scan_kernel(const int* __restrict__ flag, int64_t n, int64_t* __
   }
   __syncthreads();
   int64_t acc = part[t];
-  for (int64_t i = lo; i < hi; ++i) { pos[i] = acc; acc += flag[i]; }
+  for (int64_t i = lo; i < hi; ++i) { pos[i] = acc; acc += x[i]; }
+}
+
+// pos[i] = toff[tile] + (flags before i within its tile); 16 flags per thread
+__global__ void __launch_bounds__(256) scan_apply_kernel(const int* __restrict__ flag, int64_t n,
+                                                         const int64_t* __restrict__ toff,
+                                                         int64_t* __restrict__ pos) {
+  __shared__ int64_t part[256];
+  constexpr int per = kScanTile / 256;
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * per;
+  int v[per];
+  int64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    v[q] = base + q < n ? flag[base + q] : 0;
+    s += v[q];
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the 256 thread sums
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t acc = toff[blockIdx.x] + part[threadIdx.x] - s;
+#pragma unroll
+  for (int q = 0; q < per; ++q) {
+    if (base + q < n) pos[base + q] = acc;
+    acc += v[q];
+  }
 }
 
 __global__ void compact_kernel(const Cand* __restrict__ a, const int* __restrict__ flag, const int64_t* __restrict__ pos,
@@ -742,7 +796,15 @@ extern "C" tnb_status tnb_branch_step(tnb_beam* bm, double* p_disc_log, tnb_stre
     if (bm->pos.n < size_t(np2)) bm->pos.alloc(size_t(np2));
     if (bm->total.n < 1) bm->total.alloc(1);
     hipLaunchKernelGGL(winner_flag_kernel, dim3(nblk(np2)), dim3(256), 0, st, bm->cand.p, np2, bm->flag.p);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, bm->flag.p, np2, bm->pos.p, bm->total.p);
+    {
+      const int64_t ntile = (np2 + kScanTile - 1) / kScanTile;
+      if (bm->tsum.n < size_t(2 * ntile)) bm->tsum.alloc(size_t(2 * ntile));
+      hipLaunchKernelGGL(scan_tiles_kernel, dim3(unsigned(ntile)), dim3(256), 0, st, bm->flag.p, np2, bm->tsum.p);
+      hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, bm->tsum.p, ntile, bm->tsum.p + ntile,
+                         bm->total.p);
+      hipLaunchKernelGGL(scan_apply_kernel, dim3(unsigned(ntile)), dim3(256), 0, st, bm->flag.p, np2,
+                         bm->tsum.p + ntile, bm->pos.p);
+    }
     int64_t nw = 0;
     HIPC(hipMemcpyAsync(&nw, bm->total.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
