@@ -234,27 +234,45 @@ __device__ void jacobi_body(double* __restrict__ G, int s, double* __restrict__ 
         sn[a] = sv;
       }
       __syncthreads();
-      // rows: G <- J^T G
-      for (int idx = tid; idx < (m / 2) * s; idx += nt) {
-        int a = idx / s, k = idx % s;
-        int p = pp[a], q = qq[a];
-        if (q >= s || sn[a] == 0.0) continue;
-        double gp = G[p * s + k], gq = G[q * s + k];
-        G[p * s + k] = cs[a] * gp - sn[a] * gq;
-        G[q * s + k] = sn[a] * gp + cs[a] * gq;
-      }
-      __syncthreads();
-      // columns: G <- G J ; V <- V J
-      for (int idx = tid; idx < (m / 2) * s; idx += nt) {
-        int a = idx / s, k = idx % s;
-        int p = pp[a], q = qq[a];
-        if (q >= s || sn[a] == 0.0) continue;
-        double gp = G[k * s + p], gq = G[k * s + q];
-        G[k * s + p] = cs[a] * gp - sn[a] * gq;
-        G[k * s + q] = sn[a] * gp + cs[a] * gq;
-        double vp = V[k * s + p], vq = V[k * s + q];
-        V[k * s + p] = cs[a] * vp - sn[a] * vq;
-        V[k * s + q] = sn[a] * vp + cs[a] * vq;
+      // G <- J^T G J and V <- V J in one phase: the pairs are disjoint, so
+      // every 2x2 block (rows of pair a, columns of pair b) is updated by one
+      // thread, rows first then columns -- the same operations, in the same
+      // order, as a row pass followed by a column pass
+      const int h = m / 2;
+      for (int idx = tid; idx < h * h + h * s; idx += nt) {
+        if (idx < h * h) {
+          const int a = idx / h, b = idx % h;
+          const int pa = pp[a], qa = qq[a], pb = pp[b], qb = qq[b];
+          const bool qar = qa < s, qbr = qb < s;
+          const bool ra = qar && sn[a] != 0.0, rb = qbr && sn[b] != 0.0;
+          if (!ra && !rb) continue;
+          double xpp = G[pa * s + pb];
+          double xpq = qbr ? G[pa * s + qb] : 0.0;
+          double xqp = qar ? G[qa * s + pb] : 0.0;
+          double xqq = (qar && qbr) ? G[qa * s + qb] : 0.0;
+          if (ra) {
+            const double ypp = cs[a] * xpp - sn[a] * xqp, yqp = sn[a] * xpp + cs[a] * xqp;
+            const double ypq = cs[a] * xpq - sn[a] * xqq, yqq = sn[a] * xpq + cs[a] * xqq;
+            xpp = ypp; xqp = yqp; xpq = ypq; xqq = yqq;
+          }
+          if (rb) {
+            const double zpp = cs[b] * xpp - sn[b] * xpq, zpq = sn[b] * xpp + cs[b] * xpq;
+            const double zqp = cs[b] * xqp - sn[b] * xqq, zqq = sn[b] * xqp + cs[b] * xqq;
+            xpp = zpp; xpq = zpq; xqp = zqp; xqq = zqq;
+          }
+          G[pa * s + pb] = xpp;
+          if (qbr) G[pa * s + qb] = xpq;
+          if (qar) G[qa * s + pb] = xqp;
+          if (qar && qbr) G[qa * s + qb] = xqq;
+        } else {
+          const int jdx = idx - h * h;
+          const int a = jdx / s, k = jdx % s;
+          const int p = pp[a], q = qq[a];
+          if (q >= s || sn[a] == 0.0) continue;
+          const double vp = V[k * s + p], vq = V[k * s + q];
+          V[k * s + p] = cs[a] * vp - sn[a] * vq;
+          V[k * s + q] = sn[a] * vp + cs[a] * vq;
+        }
       }
       __syncthreads();
     }
