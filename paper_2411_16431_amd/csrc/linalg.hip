@@ -195,21 +195,20 @@ __device__ void jacobi_body(double* __restrict__ G, int s, double* __restrict__ 
       tot += g * g;
       if (idx / s != idx % s) off += g * g;
     }
+    // both sums in one tree (cs and sn, 1024 doubles together, are free here)
+    double* red2 = cs;
     red[tid] = off;
+    red2[tid] = tot;
     __syncthreads();
     for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
+      if (tid < w) {
+        red[tid] += red[tid + w];
+        red2[tid] += red2[tid + w];
+      }
       __syncthreads();
     }
     off = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    tot = red[0];
+    tot = red2[0];
     __syncthreads();
     if (!(off > 1e-30 * tot) || tot == 0.0) break;
     for (int round = 0; round < m - 1; ++round) {
