@@ -8,7 +8,7 @@ the final states and their energies.  The metric counts spin marginals: for
 every parent b at every beam step, the k marginals <s_i>_b of the cluster
 being fixed, which its conditional distribution p_b(x) determines.
 
-Prints one JSON line.  With --gpus N > 1 it exits: this build runs on one GPU.
+Prints one JSON line.  With --gpus N > 1 it exits: the implementation runs on one GPU.
 """
 import argparse
 import json
@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # configs[0]: Zephyr Z_2 (t=4, 160 spins), J ~ U[-1,1], h ~ U[-0.1,0.1],
+    # plain method on Zephyr Z_2 (t=4, 160 spins), J ~ U[-1,1], h ~ U[-0.1,0.1],
     # beta = 1, chi = 16, beam M = 64, 8 states returned, FP64.
     "zephyr_z2_t4_plain": dict(kind="zephyr", kw=dict(m=2, t=4), seed=1000, jdist="uniform",
                                hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
@@ -175,7 +175,7 @@ def planted_gap(pk, wl, env_kw):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d"
+        print("bench.py runs on one GPU only (there is no multi-GPU path); got --gpus %d"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

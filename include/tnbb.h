@@ -35,7 +35,7 @@ typedef enum {
   TNB_ENUMERIC = -3,     /* non-finite value, or every marginal of a parent
                             was non-positive                                  */
   TNB_EDEVICE = -4,      /* HIP runtime error                                  */
-  TNB_EUNSUPPORTED = -5  /* size beyond what this build supports              */
+  TNB_EUNSUPPORTED = -5  /* size beyond what the library supports           */
 } tnb_status;
 
 typedef void* tnb_stream;  /* a hipStream_t; NULL is the null stream */

@@ -46,7 +46,7 @@ def test_truncated_logz_matches_oracle(kind, kw, chi):
     ora = contract_env(inst, 1.0, Options(chi=chi, width_extra=8, power=2, cut=1e-6, seed=777))
     cl = pk.Clusters(inst, 1.0)
     env = pk.Env(cl, pk.EnvOptions(chi=chi, sketch_extra=8, power_iters=2, cut=1e-6, seed=777))
-    # spec tolerance: 1e-5 relative on log Z
+    # target tolerance: 1e-5 relative on log Z
     assert abs(env.logZ - ora.logZ) <= 1e-5 * abs(ora.logZ), (env.logZ, ora.logZ)
     for r in range(1, inst.R):
         for k, site in enumerate(ora.psi[r]):
