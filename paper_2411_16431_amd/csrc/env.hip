@@ -417,8 +417,11 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
 // has consumed its registers, overlapping stage 2 and the barriers.  Both
 // modes read P as [item][k][b] (16 consecutive b per load): MODE 1 gets the
 // MPS site as stored, MODE 0 a transposed copy of the connector, [l][g][b].
+// The register budget is capped at four waves per SIMD (128 registers, a few
+// spilled outside the item loop): the extra wave hides more load latency than
+// the spills cost.
 template <int MODE, int NJ>
-__global__ void __launch_bounds__(256) medf_bin_pipe(MedF f, const double* __restrict__ P,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const double* __restrict__ P,
                                                      const double* __restrict__ Q, int Da, int Db, int Kd, int s,
                                                      double* __restrict__ out) {
   constexpr int KK = 8, QS = 16 * NJ;  // reduction <= 4 * KK
@@ -1044,8 +1047,8 @@ struct Zipper {
                    8.0 * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
                           double(md.drd) * md.db2 * f.nHR * Db * s));
         if (Dg <= 32) {
-          // one 16-column sketch tile per workgroup keeps the register count at
-          // three waves per SIMD
+          // one 16-column sketch tile per workgroup keeps the register count
+          // within the kernel's four-waves-per-SIMD cap
           // the kernel reads the connector as [l][g][b] (contiguous along b)
           const int64_t nconn = int64_t(md.dL) * Db * Dg;
           ensure(connT, size_t(nconn));
