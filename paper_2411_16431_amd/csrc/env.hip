@@ -712,8 +712,9 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
 //   applyT: G[u]  (Dg x s)   = sum_{x in u} w(x) K[rho(x)]^T . (A[v'(x)]^T . Y[l(x)])
 // One wave per output block for apply (its x range is short); four waves
 // splitting the x range of an output block for applyT, summed through LDS.
+// apply is capped at five waves per SIMD; NJ <= 3 fits that without spilling.
 template <int NJ>
-__global__ void __launch_bounds__(64) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
                                                       uint32_t Bup, uint32_t Bdn, const double* __restrict__ w,
                                                       const double* __restrict__ A, int Da, int Db,
                                                       const double* __restrict__ Kc, int Dg,

@@ -629,6 +629,8 @@ void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double*
 // A workgroup of four waves owns a 128 x 64 tile of C; each wave a 64 x 32
 // sub-tile (4 x 2 MFMA blocks).  K advances in slices of 16 staged in LDS,
 // the next slice prefetched into registers while the current one is used.
+// The register budget is capped at three waves per SIMD, which the kernel
+// fits without spilling (the uncapped allocation allows two).
 namespace tnb {
 namespace la {
 
@@ -640,7 +642,7 @@ __device__ __forceinline__ int64_t ix_off(uint32_t i, const Ix& x) {
   return x.n0 ? int64_t(i / x.n0) * x.s1 + int64_t(i % x.n0) * x.s0 : int64_t(i) * x.s0;
 }
 
-__global__ void __launch_bounds__(256) gemm_mfma_kernel(int M, int N, int K, Operand A, Operand B, double* __restrict__ C,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) gemm_mfma_kernel(int M, int N, int K, Operand A, Operand B, double* __restrict__ C,
                                                         Ix cr, Ix cc, int64_t cbs, double alpha, double beta,
                                                         int a_kfast, int b_kfast, int tiles_n) {
   __shared__ double As[GK][GM + 1];
