@@ -55,9 +55,11 @@ __global__ void gemm_finish_kernel(int nb, int M, int N, int nchunk, const doubl
 // workgroup per (batch, chunk); wave w takes the k-steps of 4 that are w mod 4
 // in the chunk and accumulates the whole output in 16x16 MFMA tiles; the four
 // partial outputs are added in LDS in wave order, so the sum is deterministic.
+// Without a register cap the accumulators go to AGPRs and the kernel runs one
+// wave per SIMD; capped, it fits in VGPRs alone and runs three, with no spill.
 typedef double v4d_s __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) gemm_small_kernel(int M, int N, int64_t K, int64_t kchunk,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) gemm_small_kernel(int M, int N, int64_t K, int64_t kchunk,
                                                          const double* __restrict__ A, int64_t ars, int64_t acs,
                                                          int64_t abs_, const double* __restrict__ B, int64_t brs,
                                                          int64_t bcs, int64_t bbs, double* __restrict__ P,
