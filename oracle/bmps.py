@@ -21,6 +21,12 @@ the left-canonical Psi_{r+1}; at each site the dashed-box operator is
 truncated by a randomized SVD targeting 2 chi singular values (matrix-free,
 Halko et al.); afterwards a left-to-right SVD sweep truncates to chi.  All
 Boltzmann tables are shifted by their minimum energy (per-table log-scale).
+
+Pins.  The untruncated contraction is pinned to brute force and closed forms.
+The chi truncation of a boundary MPS is pinned to the TT-SVD upper bound and
+the Eckart-Young lower bound of the exact state.  The value of log Z under
+truncation has no worked values to compare with, so it is parity unpinned
+beyond those bounds and chi-convergence.
 """
 import numpy as np
 
