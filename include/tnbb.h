@@ -93,7 +93,8 @@ tnb_status tnb_bond_energies(const tnb_clusters* cl, int32_t m, int32_t n, doubl
                              int64_t n_out, int32_t* rows, int32_t* cols_out,
                              tnb_stream stream);
 
-/* Options of the boundary-MPS compression (Sec. III.C, Fig. 8). */
+/* Options of the boundary-MPS compression (Sec. III.B, "Variational zipper
+ * algorithm for boundary MPS", Fig. 8). */
 typedef struct {
   int32_t chi;           /* bond dimension of the boundary MPSs, >= 1        */
   int32_t sketch_extra;  /* oversampling: sketch width is 2*chi + extra      */

@@ -10,7 +10,7 @@ Modules
              states, closed forms.
   potts   -- Eq. (3)-(5): cluster tables E_n[x], projectors, compressed bond
              tables.
-  bmps    -- Sec. III.B-C: PEPS row transfer, zipper with randomized SVD,
+  bmps    -- Sec. III.B: PEPS row transfer, variational zipper with randomized SVD,
              truncation, log Z.
   search  -- Sec. III.A, Eq. (7)-(9): conditional marginals from the
              boundary MPS and branch and bound with boundary merging.

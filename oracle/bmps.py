@@ -1,4 +1,7 @@
-"""Boundary-MPS approximation of the lower half of the PEPS (Sec. III.B-C).
+"""Boundary-MPS approximation of the lower half of the PEPS (Sec. III.B).
+
+TEST INFRASTRUCTURE (see the package docstring): only tests, the smoke run
+and the CPU-baseline leg of the benchmark use this module.
 
 Tensor network (one fixed decomposition; the paper's Fig. 5 and A6 are not
 recoverable).  The boundary MPS Psi_r stands for all rows >= r as a function
@@ -16,17 +19,27 @@ every use goes through the diagrams below, which enumerate x (site) or
 (rho, l) (mediating), as in Fig. 7.
 
 Psi_R = 1 and Psi_r = compress_chi(T_r Psi_{r+1}) for r = R-1 .. 1, where
-compress is the zipper of Fig. 8: MPO tensors are attached right to left to
-the left-canonical Psi_{r+1}; at each site the dashed-box operator is
-truncated by a randomized SVD targeting 2 chi singular values (matrix-free,
-Halko et al.); afterwards a left-to-right SVD sweep truncates to chi.  All
-Boltzmann tables are shifted by their minimum energy (per-table log-scale).
+compress is the variational zipper of Fig. 8 (Sec. III.B, "Variational
+zipper algorithm for boundary MPS"):
+  1. MPO tensors are attached right to left to the left-canonical
+     Psi_{r+1}; at each site the dashed-box operator is truncated to 2 chi
+     singular triplets by a matrix-free randomized SVD (Halko et al.);
+  2. each zipper step is followed by a variational sweep over the two sites
+     next to the zipper centre (the new site and the one built before it);
+  3. the finished 2 chi MPS is refined by full one-site variational sweeps
+     that maximise its overlap with T_r Psi_{r+1};
+  4. a left-to-right SVD sweep truncates it to chi.
+All Boltzmann tables are shifted by their minimum energy (per-table
+log-scale).
 
 Pins.  The untruncated contraction is pinned to brute force and closed forms.
-The chi truncation of a boundary MPS is pinned to the TT-SVD upper bound and
-the Eckart-Young lower bound of the exact state.  The value of log Z under
-truncation has no worked values to compare with, so it is parity unpinned
-beyond those bounds and chi-convergence.
+The three diagram forms (apply, transpose, left transfer) are tied to each
+other by adjoint identities on random tensors.  Every variational update is
+checked never to move the state away from its target.  The chi truncation is
+pinned to the TT-SVD upper bound and the Eckart-Young lower bound of the
+exact state.  The value of log Z under truncation has no worked values to
+compare with, so it is parity unpinned beyond those bounds and
+chi-convergence.
 """
 import numpy as np
 
@@ -36,15 +49,23 @@ SPLITMIX_GOLDEN = 0x9E3779B97F4A7C15
 MASK64 = (1 << 64) - 1
 
 
-def splitmix64(c):
-    """SplitMix64 output for counter c (vectorised over uint64)."""
-    z = np.asarray(c, dtype=np.uint64)
+def splitmix64_finalize(z):
+    """The SplitMix64 output function applied to a generator state z."""
+    z = np.asarray(z, dtype=np.uint64)
     with np.errstate(over="ignore"):
-        z = (z + np.uint64(1)) * np.uint64(SPLITMIX_GOLDEN)
         z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
         z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
         z = z ^ (z >> np.uint64(31))
     return z
+
+
+def splitmix64(c):
+    """Output c of the SplitMix64 stream started from state 0, i.e. the
+    finaliser of the state (c + 1) * golden (vectorised over uint64)."""
+    z = np.asarray(c, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z + np.uint64(1)) * np.uint64(SPLITMIX_GOLDEN)
+    return splitmix64_finalize(z)
 
 
 def rademacher(n_rows, n_cols, seed, r, k):
@@ -71,6 +92,34 @@ def orth(Y, cut):
     return out
 
 
+def keep_triplets(U, S, Vt, t, cut):
+    """The leading t singular triplets of an SVD, zero-padded to t, with
+    those of sigma <= cut * sigma_max set to zero together with their
+    vectors (R7)."""
+    S = S[:t].copy()
+    U = U[:, :t].copy()
+    Vt = Vt[:t].copy()
+    if S.size and S[0] > 0:
+        drop = S <= cut * S[0]
+    else:
+        drop = np.ones(S.shape, dtype=bool)
+    S[drop] = 0.0
+    U[:, drop] = 0.0
+    Vt[drop, :] = 0.0
+    if S.size < t:                      # fewer singular values than the target
+        pad = t - S.size
+        S = np.concatenate([S, np.zeros(pad)])
+        U = np.concatenate([U, np.zeros((U.shape[0], pad))], axis=1)
+        Vt = np.concatenate([Vt, np.zeros((pad, Vt.shape[1]))], axis=0)
+    return U, S, Vt
+
+
+def svd_keep(M, t, cut):
+    """Thin SVD of M with keep_triplets applied."""
+    U, S, Vt = np.linalg.svd(M, full_matrices=False)
+    return keep_triplets(U, S, Vt, t, cut)
+
+
 def rsvd(apply, applyT, n_rows, n_cols, t, width, power, cut, seed, r, k):
     """Randomized truncated SVD of the implicit n_rows x n_cols operator D.
 
@@ -90,22 +139,7 @@ def rsvd(apply, applyT, n_rows, n_cols, t, width, power, cut, seed, r, k):
         Y = apply(orth(Z, cut))
     Q = orth(Y, cut)
     B = applyT(Q).T                     # (s, n_cols) = Q^T D
-    Ub, S, Vt = np.linalg.svd(B, full_matrices=False)
-    S = S[:t].copy()
-    Ub = Ub[:, :t].copy()
-    Vt = Vt[:t].copy()
-    if S.size and S[0] > 0:
-        drop = S <= cut * S[0]
-    else:
-        drop = np.ones(S.shape, dtype=bool)
-    S[drop] = 0.0
-    Ub[:, drop] = 0.0
-    Vt[drop, :] = 0.0
-    if S.size < t:                      # fewer singular values than the target
-        pad = t - S.size
-        S = np.concatenate([S, np.zeros(pad)])
-        Ub = np.concatenate([Ub, np.zeros((Ub.shape[0], pad))], axis=1)
-        Vt = np.concatenate([Vt, np.zeros((pad, Vt.shape[1]))], axis=0)
+    Ub, S, Vt = svd_keep(B, t, cut)
     return Q @ Ub, S, Vt
 
 
@@ -256,24 +290,26 @@ class RowOps:
     # ---- mediating diagram (Fig. 7c,d) --------------------------------------
     CHUNK = 4096
 
-    def med_apply(self, c, A, K, X):
+    def med_apply(self, c, A, K, X, rhos=None):
         """(D X)[alpha, rho, j] for the dashed box A_{2c+1} . M_c . K.
         A: (Da, da'*db', Db); K: (Db, dL, Dg); X: (da, db, Dg, s).
         W_dr depends on l only through l_d and W_dl on rho only through
-        rho_d, so both are applied to X first: X2[l_d, rho_d]."""
+        rho_d, so both are applied to X first: X2[l_d, rho_d].  With `rhos`
+        only those output rows rho are computed (in that order)."""
         M = self.med[c]
         Da = A.shape[0]
         Xa = np.einsum("al,abgj->lbgj", M["Wdr"], X)                 # (l_d, b, Dg, s)
         X2 = np.einsum("br,lbgj->lrgj", M["Wdl"], Xa)                # (l_d, rho_d, Dg, s)
-        out = np.zeros((Da, M["dR"], X.shape[-1]))
-        for rho in range(M["dR"]):
+        rhos = np.arange(M["dR"]) if rhos is None else np.asarray(rhos)
+        out = np.zeros((Da, len(rhos), X.shape[-1]))
+        for i, rho in enumerate(rhos):
             wh = self._Wh_row(M, rho)
             for l0 in range(0, M["dL"], self.CHUNK):
                 l1 = min(M["dL"], l0 + self.CHUNK)
                 X2r = X2[M["ld"][l0:l1], M["rd"][rho]]                 # (l, Dg, s)
                 T = np.einsum("blg,lgj->lbj", K[:, l0:l1, :], X2r)
                 Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"][l0:l1], :]   # (Da, l, Db)
-                out[:, rho, :] += np.einsum("alb,lbj,l->aj", Ar, T, wh[l0:l1])
+                out[:, i, :] += np.einsum("alb,lbj,l->aj", Ar, T, wh[l0:l1])
         return out
 
     def med_applyT(self, c, A, K, Y):
@@ -293,62 +329,250 @@ class RowOps:
         H = np.einsum("br,lrgj->lbgj", M["Wdl"], G2)                   # (l_d, b, Dg, s)
         return np.einsum("al,lbgj->abgj", M["Wdr"], H)
 
+    # ---- left transfers (Fig. 8d: environments of the overlap) -------------
+    def site_left(self, c, A, L, phi):
+        """Left environment one site further right, through the site diagram:
+        out[b, rho, g] = sum_{a, l, t, v} L[a, l, t] phi[t, v, g]
+                         * (A_{2c} . S_c)[(a, l), v, (b, rho)],
+        i.e. sum over x with P^R x = rho of w(x) A[:, v'(x), b]^T L[:, l(x), :]
+        (sum_v W_v(v, u(x)) phi[:, v, :]).  L: (Da, dL, t); phi: (t, d_v, g)."""
+        S = self.site[c]
+        Pt = np.einsum("vu,tvg->utg", S["Wv"], phi)                   # (d_u, t, g)
+        T = np.einsum("axt,xtg->xag", L[:, S["l"], :], Pt[S["u"]])   # (x, a, g)
+        Y = np.einsum("axb,xag->xbg", A[:, S["vd"], :], T) * S["w"][:, None, None]
+        out = _segment_sum(Y, S["rho"], S["dR"])                     # (dR, Db, g)
+        return np.transpose(out, (1, 0, 2))
+
+    def med_left(self, c, A, L, phi, ells=None):
+        """Left environment through the mediating diagram:
+        out[b, l, g] = sum_{a, rho, t, alpha, beta} L[a, rho, t] phi[t, alpha + da beta, g]
+                       * W_h(rho, l) W_dr(alpha, l_d(l)) W_dl(beta, rho_d(rho))
+                       * A[a, a'(rho) + da' b'(l), b].
+        L: (Da, dR, t); phi: (t, da*db, g).  With `ells` only those l."""
+        M = self.med[c]
+        da, db = M["Wdr"].shape[0], M["Wdl"].shape[0]
+        t, _, g = phi.shape
+        P4 = phi.reshape(t, db, da, g)                                  # [t, beta, alpha, g]
+        P2 = np.einsum("al,br,tbag->lrtg", M["Wdr"], M["Wdl"], P4)     # (l_d, rho_d, t, g)
+        ells = np.arange(M["dL"]) if ells is None else np.asarray(ells)
+        Db = A.shape[2]
+        out = np.zeros((Db, len(ells), g))
+        for i, l in enumerate(ells):
+            for r0 in range(0, M["dR"], self.CHUNK):
+                r1 = min(M["dR"], r0 + self.CHUNK)
+                rho = np.arange(r0, r1)
+                wh = M["Wh_tab"][M["hr"][rho], M["hl"][l]]                 # W_h(rho, l)
+                Ar = A[:, M["a2"][rho] + M["da2"] * M["b2"][l], :]         # (Da, rho, Db)
+                T = np.einsum("art,rtg->rag", L[:, r0:r1, :], P2[M["ld"][l], M["rd"][rho]])
+                out[:, i, :] += np.einsum("arb,rag,r->bg", Ar, T, wh)
+        return out
+
 
 def trivial_mps(dims):
     return [np.ones((1, d, 1)) for d in dims]
 
 
 class Options:
-    def __init__(self, chi, width_extra=8, power=1, cut=1e-6, seed=12345):
+    """Compression options.  var_window: sites in the variational sweep after
+    each zipper step (2: the new site and its right neighbour; 0: none).
+    var_sweeps: full one-site sweeps at 2 chi before the chi truncation."""
+
+    def __init__(self, chi, width_extra=8, power=1, cut=1e-6, seed=12345, var_window=2, var_sweeps=1):
         self.chi, self.width_extra, self.power, self.cut, self.seed = chi, width_extra, power, cut, seed
+        self.var_window, self.var_sweeps = var_window, var_sweeps
 
 
-def zipper(net, r, psi, opts, truncate=True):
+class Box:
+    """The dashed box of Fig. 8(c) at site k of the row-r zipper: site k of
+    Psi_{r+1} (A, shape (Da, ds', Db)), MPO tensor k of row r and a right
+    environment `conn` (Db, dm', Dg).  As a matrix it maps columns
+    (sigma, g) (ds * Dg) to rows (a, m) (Da * dm); sigma is the physical
+    index of Psi_r at site k."""
+
+    def __init__(self, ops, dims, split, k, A, conn):
+        self.ops, self.k, self.A, self.conn = ops, k, A, conn
+        self.Da, self.Db = A.shape[0], A.shape[2]
+        if k % 2 == 0:
+            self.c = k // 2
+            self.dm = ops.site[self.c]["dL"]
+            self.dm_out = ops.site[self.c]["dR"]
+        else:
+            self.c = (k - 1) // 2
+            self.dm = ops.med[self.c]["dR"]
+            self.dm_out = ops.med[self.c]["dL"]
+            self.da, self.db = split[k]
+        self.ds = dims[k]
+        self.Dg = conn.shape[2] if conn is not None else None
+
+    @property
+    def n_rows(self):
+        return self.Da * self.dm
+
+    def apply(self, Xf):
+        """(D X) for X (ds*Dg, s) -> (Da*dm, s)."""
+        s = Xf.shape[1]
+        if self.k % 2 == 0:
+            out = self.ops.site_apply(self.c, self.A, self.conn, Xf.reshape(self.ds, self.Dg, s))
+        else:
+            # column index sigma = a + da*b: reshape (db, da) then swap to (a, b)
+            X = Xf.reshape(self.db, self.da, self.Dg, s).transpose(1, 0, 2, 3)
+            out = self.ops.med_apply(self.c, self.A, self.conn, X)
+        return out.reshape(-1, s)
+
+    def applyT(self, Yf):
+        """(D^T Y) for Y (Da*dm, s) -> (ds*Dg, s)."""
+        s = Yf.shape[1]
+        Y = Yf.reshape(self.Da, self.dm, s)
+        if self.k % 2 == 0:
+            out = self.ops.site_applyT(self.c, self.A, self.conn, Y)
+        else:
+            out = self.ops.med_applyT(self.c, self.A, self.conn, Y).transpose(1, 0, 2, 3)
+        return out.reshape(-1, s)
+
+    def left(self, Lf, phi):
+        """Left environment after this site: Lf (Da*dm, t) over the rows of
+        the box, phi (t, ds, g) the new site -> (Db*dm', g), the rows of the
+        next site's box."""
+        t = Lf.shape[1]
+        L = Lf.reshape(self.Da, self.dm, t)
+        if self.k % 2 == 0:
+            out = self.ops.site_left(self.c, self.A, L, phi)
+        else:
+            out = self.ops.med_left(self.c, self.A, L, phi)
+        return out.reshape(-1, phi.shape[2])
+
+
+def site_cols(phi):
+    """A site (t, ds, g) as the column block X (ds*g, t) of a box."""
+    return phi.reshape(phi.shape[0], -1).T
+
+
+def window_sweep(mk_box, k, QU, S, Vt, ds, conn_right, cut, trace=None):
+    """Variational sweep over sites k and k+1 after zipper step k (R6).
+
+    The rows (a, m) of the box at k stand for the part of T_r Psi_{r+1} left
+    of the zipper centre; as in the zipper's own SVD they are taken as an
+    orthonormal basis.  In that metric the state after step k is
+    QU . (S Vt) . out[k+1] ..., with QU (rows x t) orthonormal columns.  The
+    sweep (Fig. 8d) is two one-site overlap-maximisation updates:
+      1. move the centre to k+1: S Vt = U_l R (left-canonical U_l), left
+         environment L_{k+1} = left transfer of (QU, U_l) through site k;
+         update site k+1 to L_{k+1} . (T Psi)_{k+1} . R_{k+2}, i.e. the
+         transposed box at k+1 applied to L_{k+1}; make it right-canonical and
+         recompute its right environment;
+      2. update the centre at k within the span of QU: QU^T . (T Psi)_k .
+         R_{k+1}, the transposed box at k applied to QU; split it into a
+         right-canonical site and the new connector QU . (V S).
+    Each update maximises the overlap with the target over one site with the
+    rest fixed, so the distance to the target never grows.  Returns
+    (site k, site k+1, connector at k (rows x t), connector at k+1)."""
+    t = S.size
+    Dg = Vt.shape[1] // ds
+    Ul, _, _ = svd_keep((S[:, None] * Vt).reshape(t * ds, Dg), Dg, cut)
+    phiL = Ul.reshape(t, ds, Dg)
+    L1 = mk_box(k, None).left(QU, phiL)                        # (rows at k+1, Dg)
+    b1 = mk_box(k + 1, conn_right)
+    c1 = b1.applyT(L1)                                         # (cols at k+1, Dg)
+    if trace:
+        trace(dict(k=k, stage="window k+1", chain=[QU, phiL, c1.T.reshape(Dg, b1.ds, -1)]))
+    U2, _, _ = svd_keep(c1, Dg, cut)
+    site1 = U2.T.reshape(Dg, b1.ds, -1)                       # right-canonical
+    conn1 = b1.apply(U2).reshape(b1.Da, b1.dm, Dg)
+    c0 = mk_box(k, conn1).applyT(QU)                           # (ds*Dg, t)
+    U3, S3, V3t = svd_keep(c0, t, cut)
+    site0 = U3.T.reshape(t, ds, Dg)
+    conn0 = QU @ (V3t.T * S3[None, :])
+    if trace:
+        trace(dict(k=k, stage="window k", chain=[conn0, site0, site1]))
+    return site0, site1, conn0, conn1
+
+
+def variational_sweeps(mk_box, phi, n_sweeps, cut, trace=None):
+    """One-site variational sweeps of the MPS phi (list of (Dl, d, Dr); the
+    first site carries the norm, the others are right-canonical) towards the
+    target T_r Psi_{r+1} (Fig. 8d, Verstraete et al.).  The centre visits
+    0, 1, .., K-1, K-2, .., 0 in the first sweep and 1, .., K-1, .., 0 in every
+    further one.  At each visit the centre becomes L_k . (T Psi)_k . R_{k+1}
+    (the transposed box applied to the left environment), which maximises the
+    overlap over that site with the others fixed; moving on, it is split by
+    an SVD into a canonical site and a factor carried to the next site, and
+    the environment on the side it leaves is extended.  Returns phi with the
+    norm in site 0 and the other sites right-canonical."""
+    K = len(phi)
+    phi = [p.copy() for p in phi]
+    R = [None] * (K + 1)
+    R[K] = np.ones((1, 1, 1))
+    for k in range(K - 1, 0, -1):
+        b = mk_box(k, R[k + 1])
+        R[k] = b.apply(site_cols(phi[k])).reshape(b.Da, b.dm, phi[k].shape[0])
+    L = [None] * K
+    L[0] = np.ones((1, 1))
+    seq = list(range(K)) + list(range(K - 2, -1, -1))
+    for _ in range(n_sweeps - 1):
+        seq += list(range(1, K)) + list(range(K - 2, -1, -1))
+    for i, k in enumerate(seq):
+        b = mk_box(k, R[k + 1])
+        t = L[k].shape[1]
+        phi[k] = b.applyT(L[k]).T.reshape(t, b.ds, -1)
+        if trace:
+            trace(dict(k=k, stage="sweep", phi=[p.copy() for p in phi]))
+        nxt = seq[i + 1] if i + 1 < len(seq) else None
+        if nxt == k + 1:
+            Dg = phi[k].shape[2]
+            U, S, Vt = svd_keep(phi[k].reshape(t * b.ds, Dg), Dg, cut)
+            phi[k] = U.reshape(t, b.ds, Dg)
+            phi[k + 1] = np.einsum("ij,jdx->idx", S[:, None] * Vt, phi[k + 1])
+            L[k + 1] = mk_box(k, None).left(L[k], phi[k])
+        elif nxt == k - 1:
+            U, S, Vt = svd_keep(site_cols(phi[k]), t, cut)
+            phi[k] = U.T.reshape(t, b.ds, -1)
+            phi[k - 1] = np.einsum("adj,jt->adt", phi[k - 1], Vt.T * S[None, :])
+            R[k] = b.apply(U).reshape(b.Da, b.dm, t)
+    return phi
+
+
+def zipper(net, r, psi, opts, truncate=True, trace=None):
     """compress(T_r Psi_{r+1}); psi is the left-canonical Psi_{r+1} (list of
     (Dl, d, Dr) tensors).  Returns (sites of Psi_r, log of the norm factored
-    out)."""
+    out).  With truncate=False (the top row, whose contraction is exact)
+    only the zipper runs.  `trace`, if given, is called with the state after
+    every zipper step and every variational update (tests)."""
     ops = RowOps(net, r)
     C = net.C
     K = 2 * C - 1
     dims, split = net.phys_dims(r)
     chi = opts.chi
     width = 2 * chi + opts.width_extra
-    conn = np.ones((1, 1, 1))
+    mk_box = lambda k, conn: Box(ops, dims, split, k, psi[k], conn)
+    conns = [None] * (K + 1)
+    conns[K] = np.ones((1, 1, 1))
     out = [None] * K
     for k in reversed(range(K)):
-        A = psi[k]
-        Da, Dg = A.shape[0], conn.shape[2]
-        if k % 2 == 0:
-            c = k // 2
-            dm = ops.site[c]["dL"]
-            ds = dims[k]
-            app = lambda Xf, c=c, A=A, K_=conn, ds=ds, Dg=Dg: ops.site_apply(
-                c, A, K_, Xf.reshape(ds, Dg, -1)).reshape(-1, Xf.shape[1])
-            appT = lambda Yf, c=c, A=A, K_=conn, Da=Da, dm=dm: ops.site_applyT(
-                c, A, K_, Yf.reshape(Da, dm, -1)).reshape(-1, Yf.shape[1])
-        else:
-            c = (k - 1) // 2
-            dm = ops.med[c]["dR"]
-            da, db = split[k]
-            ds = da * db
-            # column index sigma = a + da*b: reshape (db, da) then swap to (a, b)
-            app = lambda Xf, c=c, A=A, K_=conn, da=da, db=db, Dg=Dg: ops.med_apply(
-                c, A, K_, Xf.reshape(db, da, Dg, -1).transpose(1, 0, 2, 3)).reshape(-1, Xf.shape[1])
-            appT = lambda Yf, c=c, A=A, K_=conn, Da=Da, dm=dm: ops.med_applyT(
-                c, A, K_, Yf.reshape(Da, dm, -1)).transpose(1, 0, 2, 3).reshape(-1, Yf.shape[1])
-        n_rows, n_cols = Da * dm, ds * Dg
+        box = mk_box(k, conns[k + 1])
+        n_rows, n_cols = box.n_rows, box.ds * box.Dg
         t = min(2 * chi, n_rows, n_cols)
-        QU, S, Vt = rsvd(app, appT, n_rows, n_cols, t, width, opts.power, opts.cut,
+        QU, S, Vt = rsvd(box.apply, box.applyT, n_rows, n_cols, t, width, opts.power, opts.cut,
                          opts.seed, r, k)
-        out[k] = Vt.reshape(t, ds, Dg)
-        conn = (QU * S[None, :]).reshape(Da, dm, t)
-    scalar = conn.reshape(-1)[0]
-    out[0] = out[0] * np.sign(scalar) if scalar != 0 else out[0]
-    logn = np.log(abs(scalar)) if scalar != 0 else -np.inf
-    if truncate:
-        out, ln2 = truncate_sweep(out, chi, opts.cut)
-        logn += ln2
-    return out, logn
+        out[k] = Vt.reshape(t, box.ds, box.Dg)
+        conns[k] = (QU * S).reshape(box.Da, box.dm, t)
+        if trace:
+            trace(dict(k=k, stage="zipper", chain=[QU * S, out[k]] + out[k + 1:]))
+        if truncate and opts.var_window >= 2 and k + 1 < K:
+            tail = out[k + 2:]
+            wtrace = (lambda d: trace(dict(d, chain=d["chain"] + tail))) if trace else None
+            out[k], out[k + 1], conn0, conn1 = window_sweep(mk_box, k, QU, S, Vt, box.ds, conns[k + 2],
+                                                             opts.cut, wtrace)
+            conns[k + 1] = conn1
+            conns[k] = conn0.reshape(box.Da, box.dm, t)
+    scalar = conns[0].reshape(-1)[0]
+    if not truncate:
+        out[0] = out[0] * np.sign(scalar) if scalar != 0 else out[0]
+        logn = np.log(abs(scalar)) if scalar != 0 else -np.inf
+        return out, logn
+    out[0] = out[0] * scalar
+    if opts.var_sweeps > 0:
+        out = variational_sweeps(mk_box, out, opts.var_sweeps, opts.cut, trace)
+    return truncate_sweep(out, chi, opts.cut)
 
 
 def truncate_sweep(sites, chi, cut):

@@ -1,4 +1,4 @@
-// Boundary-MPS contraction (Sec. III.B-C): row transfer T_r applied to
+// Boundary-MPS contraction (Sec. III.B): row transfer T_r applied to
 // Psi_{r+1} by a right-to-left zipper; each dashed box is compressed by a
 // matrix-free randomized SVD (range finder with a SplitMix64 Rademacher
 // sketch, subspace iterations, Gram-based thin SVD in FP64), then a

@@ -96,3 +96,24 @@ def test_orth_drops_numerical_null_space():
     Y = np.outer(np.arange(1.0, 6.0), np.ones(3))
     Q = orth(Y, 1e-10)
     assert np.allclose(Q[:, 1:], 0) and abs(np.linalg.norm(Q[:, 0]) - 1) < 1e-14
+
+
+def test_splitmix64_matches_published_outputs():
+    # SplitMix64 (Steele, Lea, Flood 2014): the stream from seed 1234567 begins
+    # 6457827717110365317, 3203168211198807973, 9817491932198370423,
+    # 4593380528125082431, 16408922859458223821 (Rosetta Code, "Pseudo-random
+    # numbers/Splitmix64"), and the stream from seed 0 begins 0xe220a8397b1dcdaf.
+    # State k of a stream is seed + k * golden.
+    from oracle.bmps import splitmix64, splitmix64_finalize, SPLITMIX_GOLDEN
+    from tnb_inputs import splitmix64 as inputs_splitmix64
+    g = SPLITMIX_GOLDEN
+    states = np.array([(1234567 + k * g) % (1 << 64) for k in range(1, 6)], dtype=np.uint64)
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    assert [int(v) for v in splitmix64_finalize(states)] == want
+    assert int(splitmix64(np.uint64(0))) == 0xE220A8397B1DCDAF
+    assert int(inputs_splitmix64(np.uint64(0))) == 0xE220A8397B1DCDAF
+    # counter c is state (c + 1) * golden of the seed-0 stream
+    c = np.arange(5, dtype=np.uint64)
+    ref = splitmix64_finalize(np.array([((int(i) + 1) * g) % (1 << 64) for i in c], dtype=np.uint64))
+    assert np.array_equal(splitmix64(c), ref) and np.array_equal(inputs_splitmix64(c), ref)

@@ -66,11 +66,94 @@ def test_conditional_marginal_mid_row_matches_brute_force():
 
 
 def test_marginals_sum_to_one_and_are_probabilities():
+    # every parent's conditional distribution at every step of a truncated
+    # run (chi = 4): entries in [0, 1], summing to one
+    inst = make_instance("zephyr", 53, jdist="uniform", hdist="uniform0.1", m=1, t=2)
+    env = contract_env(inst, 1.0, Options(chi=4))
+    res = solve(inst, 1.0, env, M=16, K=4, trace=True)
+    for rec in res["steps"]:
+        p = rec["p"]
+        assert np.all(p >= 0) and np.all(p <= 1)
+        assert np.allclose(p.sum(axis=1), 1.0, atol=1e-12)
+
+
+def test_returned_energies_sorted_and_recomputed():
     inst = make_instance("zephyr", 53, jdist="uniform", hdist="uniform0.1", m=1, t=2)
     env = contract_env(inst, 1.0, Options(chi=4))
     res = solve(inst, 1.0, env, M=16, K=4)
     assert np.all(np.diff(res["energies"]) >= 0)
     assert np.array_equal(res["energies"], ising.energies(inst, res["states"]))
+
+
+def _brute_beam(inst, beta, M):
+    """Branch and bound with probabilities from brute-force enumeration
+    (Sec. III.A): the chain-rule score of a partial configuration is then the
+    log of its exact marginal probability.  The boundary of a partial
+    configuration is the set of fixed spins with a coupling to an unfixed spin
+    (Eq. 8), compared by value.  Group winners and the top M go to the larger
+    score, ties to the smaller (parent, x); no merge once the boundary is
+    empty; p_d is the best top-M loser over all steps."""
+    P = Potts(inst)
+    N, ncell = inst.n_spins, P.R * P.C
+    x = np.arange(1 << N)
+    s = ((x[:, None] >> np.arange(N)) & 1) * 2 - 1
+    E = (s[:, inst.edges[:, 0]] * s[:, inst.edges[:, 1]]) @ inst.J + s @ inst.h
+    w = np.exp(-beta * (E - E.min()))
+    w /= w.sum()
+    X = P.cluster_of_states(s)                        # (2^N, cells)
+    parents = [()]
+    pd_log = -np.inf
+    steps = []
+    for n in range(ncell):
+        fixed_cells = set(range(n + 1))
+        bnd = sorted({int(i) for (i, j) in inst.edges if (inst.cell_of[i] in fixed_cells) != (inst.cell_of[j] in fixed_cells)
+                      for i in ((i,) if inst.cell_of[i] in fixed_cells else (j,))})
+        cands = []
+        for b, par in enumerate(parents):
+            match = np.all(X[:, :n] == np.array(par, dtype=np.int64)[None, :], axis=1) if n else np.ones(len(x), bool)
+            for xv in range(1 << int(P.k[n])):
+                m = match & (X[:, n] == xv)
+                pm = w[m].sum()
+                if pm <= 0:
+                    continue
+                conf = par + (xv,)
+                spins_b = s[np.flatnonzero(m)[0]]
+                key = tuple(int(spins_b[i]) for i in bnd)
+                cands.append((np.log(pm), b, xv, key, conf))
+        cands.sort(key=lambda c: (-c[0], c[1], c[2]))
+        if bnd:
+            seen, win = set(), []
+            for c in cands:
+                if c[3] not in seen:
+                    seen.add(c[3])
+                    win.append(c)
+        else:
+            win = cands
+        if len(win) > M:
+            pd_log = max(pd_log, win[M][0])
+        keep = win[:M]
+        steps.append(([(c[4], c[0]) for c in keep], pd_log))
+        parents = [c[4] for c in keep]
+    return steps, pd_log
+
+
+@pytest.mark.parametrize("kind,kw,M", [("king", dict(R=3, C=3, a=1), 3), ("king", dict(R=4, C=4, a=1), 4),
+                                       ("king", dict(R=2, C=2, a=2), 5), ("king", dict(R=3, C=4, a=1), 2)])
+def test_largest_discarded_probability_matches_brute_force_beam(kind, kw, M):
+    inst = make_instance(kind, 63, jdist="uniform", hdist="uniform0.1", **kw)
+    beta = 1.5
+    env = contract_env(inst, beta, Options(chi=128, cut=1e-13))
+    res = solve(inst, beta, env, M=M, K=1, trace=True)
+    bsteps, bpd = _brute_beam(inst, beta, M)
+    assert np.isfinite(bpd)
+    assert abs(res["p_d_log"] - bpd) < 1e-9
+    assert len(res["steps"]) == len(bsteps)
+    for rec, (bs, bpd_n) in zip(res["steps"], bsteps):
+        got = sorted((tuple(int(v) for v in row[: rec["n"] + 1]), lp) for row, lp in zip(rec["X"], rec["logp"]))
+        ref = sorted(bs)
+        assert [g[0] for g in got] == [r[0] for r in ref]
+        assert np.allclose([g[1] for g in got], [r[1] for r in ref], atol=1e-9)
+        assert rec["p_d_log"] == bpd_n == -np.inf or abs(rec["p_d_log"] - bpd_n) < 1e-9
 
 
 @pytest.mark.parametrize("kind,kw", [("king", dict(R=3, C=3, a=1)), ("king", dict(R=4, C=5, a=1)),

@@ -1,5 +1,5 @@
 """Truncated boundary MPS of the oracle against the mathematics of MPS
-truncation (Sec. III.C, Fig. 8).
+truncation (Sec. III.B, "Variational zipper algorithm for boundary MPS", Fig. 8).
 
 The zipper first compresses T_r Psi_{r+1} to bond 2 chi.  Where that stage is
 exact, its result is right-canonical, and the left-to-right SVD sweep down to
