@@ -102,19 +102,57 @@ typedef struct {
   double cut;            /* singular values below cut*sigma_max are dropped;
                             1e-7 <= cut < 1                                  */
   uint64_t seed;         /* Rademacher sketch seed (SplitMix64, counter-based)*/
+  int32_t var_window;    /* 2: after each zipper step, one-site variational
+                            updates of the new site and its right neighbour
+                            (Fig. 8d); 0: none                               */
+  int32_t var_sweeps;    /* full one-site variational sweeps of the 2*chi MPS
+                            before the chi truncation, 0 .. 8                */
 } tnb_env_opts;
 
 /* Boundary MPSs Psi_R .. Psi_1 of the lower half-lattice (Fig. 6, 8) and
  * log Z (Eq. 10).  Psi_r (2*cols-1 sites: a vertical and a two-diagonal
- * site per column pair) is compress_chi(T_r Psi_{r+1}): a right-to-left
- * zipper attaching one site or mediating tensor at a time, each dashed box
- * truncated to 2*chi by a matrix-free randomized SVD, then a left-to-right
- * SVD sweep to chi.  log_z (host, may be NULL) receives log Z.  The returned
+ * site per column pair) is compress_chi(T_r Psi_{r+1}), the variational
+ * zipper of Sec. III.B: a right-to-left zipper attaching one site or
+ * mediating tensor at a time, each dashed box truncated to 2*chi by a
+ * matrix-free randomized SVD and followed by a one-site variational update
+ * of the two sites next to the zipper centre (var_window); then var_sweeps
+ * full one-site variational sweeps at 2*chi that maximise the overlap with
+ * T_r Psi_{r+1}; then a left-to-right SVD sweep to chi.  log_z (host, may be NULL) receives log Z.  The returned
  * handle keeps a reference to `cl`, which must outlive it.
  * Errors: TNB_EINVAL (options), TNB_ENUMERIC (zero or non-finite
  * contraction), TNB_ENOMEM. */
 tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opts, tnb_stream stream,
                             tnb_env** out, double* log_z);
+
+/* Test and measurement entry points for one dashed box of the zipper
+ * (Fig. 7 and Fig. 8c): the row-r MPO tensor at site k of Psi_r (k even:
+ * the site tensor of column k/2, Fig. 7a-b; k odd: the mediating tensor
+ * between columns (k-1)/2 and (k+1)/2, Fig. 7c-d) between site k of
+ * Psi_{r+1} below and a connector on its right.  0 <= r < rows.
+ * tnb_diagram_dims: *dm_in is the MPO bond on the box's left (its matrix has
+ * rows [m][a], m < dm_in, a < Da), *dm_out the MPO bond on its right (the
+ * connector's first index), *ds the physical dimension of Psi_r at k and
+ * *ds_below that of Psi_{r+1} at k; any pointer may be NULL. */
+tnb_status tnb_diagram_dims(const tnb_clusters* cl, int32_t r, int32_t k, int32_t* dm_in,
+                            int32_t* dm_out, int32_t* ds, int32_t* ds_below);
+
+/* Apply the box to caller tensors (device, FP64, row-major), queued on
+ * `stream` and synchronised before return.  d_A: site k of Psi_{r+1},
+ * [ds_below][Da][Db].
+ *  mode 0, D X:  d_K connector [dm_out][Db][Dg]; d_X [ds][Dg][s] (rows
+ *                (sigma, g)); d_out [dm_in][Da][s].
+ *  mode 1, D^T Y: d_K as in mode 0; d_X [dm_in][Da][s]; d_out [ds][Dg][s].
+ *  mode 2, left transfer (the environment of the overlap one site further
+ *                right, Fig. 8d): d_K the left environment [dm_in][Da][Dg];
+ *                d_X the new site [ds][Dg][s]; d_out [dm_out][Db][s].
+ * 1 <= Da, Db, Dg <= 128, 1 <= s <= 256; out_len is d_out's capacity in
+ * doubles.  The product path of tnb_contract_env runs the same kernels.
+ * Errors: TNB_EINVAL (handle, indices, sizes, NULL tensors),
+ * TNB_EUNSUPPORTED (tiles beyond the LDS), TNB_ENOMEM. */
+tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32_t mode,
+                             const double* d_A, int32_t Da, int32_t Db, const double* d_K,
+                             int32_t Dg, const double* d_X, int32_t s, double* d_out,
+                             int64_t out_len, tnb_stream stream);
 
 /* Norm-free diagnostic: number of sites of Psi_r and the shape of site k. */
 tnb_status tnb_env_site_shape(const tnb_env* env, int32_t r, int32_t k, int32_t* dl,
@@ -154,6 +192,18 @@ tnb_status tnb_branch_step(tnb_beam* beam, double* p_disc_log, tnb_stream stream
  * *count (host) receives min(K, n_parents). */
 tnb_status tnb_beam_export(const tnb_beam* beam, int32_t K, int8_t* d_states, double* d_logp,
                            int32_t* count, tnb_stream stream);
+
+/* Final selection of a finished beam (every cluster fixed): the energies
+ * of all candidates by Eq. (1) (as tnb_energies, bit for bit), and the K
+ * lowest distinct configurations, ordered by energy and then by their spin
+ * vectors lexicographically (spin 0 first, -1 < +1).  d_states (device,
+ * int8 [K][n_spins] of +-1) and d_E (device, [K]) receive them; *count
+ * (host, may be NULL) the number written, min(K, distinct candidates).
+ * The last branching step does not merge, so the candidates are the M
+ * most probable completions (Sec. III.A).  Synchronises `stream`.
+ * Errors: TNB_EINVAL (handle, K < 0, NULL outputs, unfinished beam). */
+tnb_status tnb_beam_lowest(tnb_beam* beam, int32_t K, int8_t* d_states, double* d_E, int32_t* count,
+                           tnb_stream stream);
 
 /* Layout of the row moments at the current step n = (r, c): the spins of
  * the unfixed clusters (r, c) .. (r, cols-1), cluster by cluster in

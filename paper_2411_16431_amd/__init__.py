@@ -7,8 +7,8 @@ loudly if it has not been built.
 """
 from .api import (TnbError, energies, Clusters, Env, Beam, EnvOptions, solve, library_path,
                   exported_symbols, profile_enable, profile_query, profile_names, FirstRowLogZ,
-                  first_row_layout)
+                  first_row_layout, diagram_dims, diagram_apply)
 
 __all__ = ["TnbError", "energies", "Clusters", "Env", "Beam", "EnvOptions", "solve",
            "library_path", "exported_symbols", "profile_enable", "profile_query", "profile_names",
-           "FirstRowLogZ", "first_row_layout"]
+           "FirstRowLogZ", "first_row_layout", "diagram_dims", "diagram_apply"]

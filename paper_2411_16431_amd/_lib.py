@@ -17,7 +17,8 @@ class TnbInstance(ctypes.Structure):
 
 class TnbEnvOpts(ctypes.Structure):
     _fields_ = [("chi", c_int32), ("sketch_extra", c_int32), ("power_iters", c_int32),
-                ("cut", c_double), ("seed", ctypes.c_uint64)]
+                ("cut", c_double), ("seed", ctypes.c_uint64), ("var_window", c_int32),
+                ("var_sweeps", c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -29,11 +30,16 @@ SIGNATURES = {
                                     P(c_int32), c_void_p]),
     "tnb_contract_env": (c_int32, [c_void_p, P(TnbEnvOpts), c_void_p, P(c_void_p), P(c_double)]),
     "tnb_env_site_shape": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int32), P(c_int32)]),
+    "tnb_diagram_dims": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int32), P(c_int32),
+                                   P(c_int32)]),
+    "tnb_diagram_apply": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32,
+                                    c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
     "tnb_beam_create": (c_int32, [c_void_p, c_int32, P(c_void_p)]),
     "tnb_beam_info": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),
     "tnb_marginals": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     "tnb_branch_step": (c_int32, [c_void_p, P(c_double), c_void_p]),
     "tnb_beam_export": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
+    "tnb_beam_lowest": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_row_layout": (c_int32, [c_void_p, P(c_int32), P(c_int32), c_void_p, c_void_p, c_int32]),
     "tnb_row_moments": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
     "tnb_row_moments_per_branch": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),

@@ -119,9 +119,12 @@ class EnvOptions:
     power_iters: int = 2
     cut: float = 1e-6
     seed: int = 12345
+    var_window: int = 2
+    var_sweeps: int = 1
 
     def c(self):
-        return L.TnbEnvOpts(self.chi, self.sketch_extra, self.power_iters, self.cut, self.seed)
+        return L.TnbEnvOpts(self.chi, self.sketch_extra, self.power_iters, self.cut, self.seed,
+                            self.var_window, self.var_sweeps)
 
 
 class Env(_Handle):
@@ -201,6 +204,16 @@ class Beam(_Handle):
         _check(L.lib().tnb_row_moments_per_branch(self._h, ctypes.c_void_p(m1.data_ptr()), m1.numel(), _stream()))
         return m1
 
+    def lowest(self, K, n_spins):
+        """tnb_beam_lowest: (states int8 [k, N], energies [k]) of a finished beam."""
+        import torch
+        st = torch.empty((max(K, 1), n_spins), dtype=torch.int8, device="cuda")
+        E = torch.empty(max(K, 1), dtype=torch.float64, device="cuda")
+        cnt = ctypes.c_int32()
+        _check(L.lib().tnb_beam_lowest(self._h, int(K), ctypes.c_void_p(st.data_ptr()),
+                                       ctypes.c_void_p(E.data_ptr()), ctypes.byref(cnt), _stream()))
+        return st[:cnt.value], E[:cnt.value]
+
     def export(self, K, n_spins):
         import torch
         st = torch.empty((K, n_spins), dtype=torch.int8, device="cuda")
@@ -209,6 +222,41 @@ class Beam(_Handle):
         _check(L.lib().tnb_beam_export(self._h, int(K), ctypes.c_void_p(st.data_ptr()),
                                        ctypes.c_void_p(lp.data_ptr()), ctypes.byref(cnt), _stream()))
         return st[:cnt.value], lp[:cnt.value]
+
+
+def diagram_dims(clusters, r, k):
+    """(dm_in, dm_out, ds, ds_below) of the box at site k of row r (tnb_diagram_dims)."""
+    a, b, c, d = (ctypes.c_int32() for _ in range(4))
+    _check(L.lib().tnb_diagram_dims(clusters._h, int(r), int(k), ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c), ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
+
+
+def diagram_apply(clusters, r, k, mode, A, K, X):
+    """tnb_diagram_apply on float64 cuda tensors: A [ds_below][Da][Db],
+    K [dm_out][Db][Dg] (modes 0, 1) or [dm_in][Da][Dg] (mode 2), X as in the
+    header; returns the output tensor."""
+    import torch
+    dm_in, dm_out, ds, _ = diagram_dims(clusters, r, k)
+    Da, Db = A.shape[1], A.shape[2]
+    Dg = K.shape[2]
+    if mode == 0:
+        s = X.shape[2]
+        shape = (dm_in, Da, s)
+    elif mode == 1:
+        s = X.shape[2]
+        shape = (ds, Dg, s)
+    else:
+        s = X.shape[2]
+        shape = (dm_out, Db, s)
+    for t in (A, K, X):
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    out = torch.empty(shape, dtype=torch.float64, device=A.device)
+    _check(L.lib().tnb_diagram_apply(clusters._h, int(r), int(k), int(mode), ctypes.c_void_p(A.data_ptr()),
+                                     int(Da), int(Db), ctypes.c_void_p(K.data_ptr()), int(Dg),
+                                     ctypes.c_void_p(X.data_ptr()), int(s), ctypes.c_void_p(out.data_ptr()),
+                                     out.numel(), _stream()))
+    return out
 
 
 def solve(inst, beta, chi, M, K=8, **env_kw):
@@ -225,21 +273,9 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
         _, npar, d = beam.info()
         marg += npar * int(round(math.log2(d)))
         pd = beam.step()
-    states, logp = beam.export(M, inst.n_spins)
-    E = energies(inst, states)
-    Eh, Sh = E.cpu().numpy(), states.cpu().numpy()
-    order = np.lexsort(tuple(Sh[:, ::-1].T) + (Eh,))
-    seen, keep = set(), []
-    for i in order:
-        key = Sh[i].tobytes()
-        if key not in seen:
-            seen.add(key)
-            keep.append(i)
-        if len(keep) == K:
-            break
-    keep = np.array(keep, dtype=np.int64)
-    return dict(states=Sh[keep], energies=Eh[keep], logZ=env.logZ, p_d_log=pd, env=env, beam=beam,
-                spin_marginals=marg)
+    states, E = beam.lowest(K, inst.n_spins)
+    return dict(states=states.cpu().numpy(), energies=E.cpu().numpy(), logZ=env.logZ, p_d_log=pd, env=env,
+                beam=beam, spin_marginals=marg)
 
 
 def first_row_layout(inst, beta=1.0):

@@ -77,6 +77,10 @@ struct tnb_beam {
   tnb::DevBuf<int32_t> items;
   tnb::DevBuf<double> lam, lh, vp, qa, zs, zl, rt0, rt1;
   tnb::DevBuf<int32_t> iota;
+  // final selection: exported candidates, their energies, duplicate flags
+  tnb::DevBuf<int8_t> sel_states;
+  tnb::DevBuf<double> sel_E;
+  tnb::DevBuf<int> sel_dup;
 };
 
 namespace tnb {
@@ -100,5 +104,10 @@ void normalise_rows(double* R, int64_t per, int nb, double* logs, hipStream_t st
 // q of the current column for every parent against right environments Rc
 // (parent b reads row rid[b] of Rc; column geometry cc; T must be in place).
 void q_against(tnb_beam* bm, const BCol& cc, const double* Rc, const int32_t* rid, double* q, hipStream_t st);
+// Eq. (1) for K states [K][N] of +-1 (clusters.hip): edges in order, then fields, no FMA.
+__global__ void ising_energy_kernel(const int8_t* __restrict__ s, int64_t K, int N, int E,
+                                    const int* __restrict__ ei, const int* __restrict__ ej,
+                                    const double* __restrict__ J, const double* __restrict__ h,
+                                    double* __restrict__ out);
 
 }  // namespace tnb

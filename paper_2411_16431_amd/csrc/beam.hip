@@ -485,6 +485,60 @@ __global__ void export_kernel(const int32_t* __restrict__ X, int ncell, int nfix
   if (lp_out && j == 0) lp_out[i] = logp[i];
 }
 
+// Final selection (the K lowest distinct states).  Candidate j precedes i
+// when its energy is lower, or equal with a spin vector that is smaller
+// lexicographically (spin 0 first, -1 < +1).
+__device__ inline bool sel_less(const int8_t* __restrict__ S, const double* __restrict__ E, int N, int j, int i) {
+  if (E[j] != E[i]) return E[j] < E[i];
+  const int8_t* a = S + int64_t(j) * N;
+  const int8_t* b = S + int64_t(i) * N;
+  for (int q = 0; q < N; ++q)
+    if (a[q] != b[q]) return a[q] < b[q];
+  return false;
+}
+
+// dup[i] = 1 when an earlier candidate holds the same spin vector (one
+// workgroup per candidate).
+__global__ void sel_dup_kernel(const int8_t* __restrict__ S, const double* __restrict__ E, int n, int N,
+                               int* __restrict__ dup) {
+  __shared__ int found;
+  const int i = blockIdx.x;
+  if (threadIdx.x == 0) found = 0;
+  __syncthreads();
+  const int8_t* b = S + int64_t(i) * N;
+  for (int j = threadIdx.x; j < i; j += blockDim.x) {
+    if (E[j] != E[i]) continue;
+    const int8_t* a = S + int64_t(j) * N;
+    bool same = true;
+    for (int q = 0; q < N && same; ++q) same = a[q] == b[q];
+    if (same) found = 1;  // every writer stores the same value
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) dup[i] = found;
+}
+
+// Rank of every distinct candidate among the distinct ones; the first K go
+// to the output in rank order (one workgroup per candidate).
+__global__ void sel_rank_kernel(const int8_t* __restrict__ S, const double* __restrict__ E,
+                                const int* __restrict__ dup, int n, int N, int K, int8_t* __restrict__ out_S,
+                                double* __restrict__ out_E) {
+  __shared__ int cnt[256];
+  const int i = blockIdx.x;
+  if (dup[i]) return;  // uniform over the workgroup
+  int c = 0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) c += (!dup[j] && sel_less(S, E, N, j, i)) ? 1 : 0;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    __syncthreads();
+  }
+  const int r = cnt[0];
+  if (r >= K) return;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) out_S[int64_t(r) * N + q] = S[int64_t(i) * N + q];
+  if (threadIdx.x == 0) out_E[r] = E[i];
+}
+
 __global__ void fill_d(double* __restrict__ x, int64_t n, double v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -869,6 +923,39 @@ extern "C" tnb_status tnb_beam_export(const tnb_beam* bm, int32_t K, int8_t* d_s
     HIPC(hipGetLastError());
     if (count) *count = k;
     HIPC(hipStreamSynchronize(st));
+  });
+}
+
+extern "C" tnb_status tnb_beam_lowest(tnb_beam* bm, int32_t K, int8_t* d_states, double* d_E, int32_t* count,
+                                      tnb_stream stream) {
+  return guarded([&] {
+    if (!bm || bm->kind != KIND_BEAM) fail(TNB_EINVAL, "not a beam handle");
+    if (K < 0 || (K > 0 && (!d_states || !d_E))) fail(TNB_EINVAL, "bad output");
+    if (bm->step != bm->ncell) fail(TNB_EINVAL, "the beam has unfixed clusters");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const tnb_clusters* cl = bm->env->cl;
+    const Lattice& L = cl->lat;
+    const int n = bm->npar, N = L.N;
+    int found = 0;
+    if (n > 0 && K > 0) {
+      if (bm->sel_states.n < size_t(n) * N) bm->sel_states.alloc(size_t(n) * N);
+      if (bm->sel_E.n < size_t(n)) bm->sel_E.alloc(size_t(n));
+      if (bm->sel_dup.n < size_t(n)) bm->sel_dup.alloc(size_t(n));
+      hipLaunchKernelGGL(export_kernel, dim3(nblk(int64_t(n) * N)), dim3(256), 0, st, bm->X.p, bm->ncell, bm->step,
+                         bm->cell_of.p, bm->bit.p, N, n, bm->sel_states.p, bm->logp.p, nullptr);
+      hipLaunchKernelGGL(ising_energy_kernel, dim3(nblk(n, 128)), dim3(128), 0, st, bm->sel_states.p, int64_t(n), N,
+                         L.E, cl->d_ei.p, cl->d_ej.p, cl->d_J.p, cl->d_h.p, bm->sel_E.p);
+      hipLaunchKernelGGL(sel_dup_kernel, dim3(n), dim3(256), 0, st, bm->sel_states.p, bm->sel_E.p, n, N,
+                         bm->sel_dup.p);
+      hipLaunchKernelGGL(sel_rank_kernel, dim3(n), dim3(256), 0, st, bm->sel_states.p, bm->sel_E.p, bm->sel_dup.p, n,
+                         N, K, d_states, d_E);
+      HIPC(hipGetLastError());
+      std::vector<int> dup(n);
+      HIPC(hipMemcpyAsync(dup.data(), bm->sel_dup.p, size_t(n) * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      for (int v : dup) found += v ? 0 : 1;
+    }
+    if (count) *count = std::min(K, found);
   });
 }
 

@@ -335,6 +335,11 @@ extern "C" tnb_status tnb_build_clusters(const tnb_instance* inst, double beta, 
       shift += -beta * bmin[t];
     }
     cl->shift = shift;
+    cl->d_ei.upload(L.ei, s);
+    cl->d_ej.upload(L.ej, s);
+    cl->d_J.upload(L.J, s);
+    cl->d_h.upload(L.h, s);
+    HIPC(hipStreamSynchronize(s));
     *out = cl.release();
   });
 }

@@ -1,8 +1,10 @@
 // Boundary-MPS contraction (Sec. III.B): row transfer T_r applied to
-// Psi_{r+1} by a right-to-left zipper; each dashed box is compressed by a
-// matrix-free randomized SVD (range finder with a SplitMix64 Rademacher
-// sketch, subspace iterations, Gram-based thin SVD in FP64), then a
-// left-to-right SVD sweep truncates to chi.
+// Psi_{r+1} by the variational zipper (Fig. 8): right to left, each dashed
+// box is compressed by a matrix-free randomized SVD (range finder with a
+// SplitMix64 Rademacher sketch, subspace iterations, Gram-based thin SVD in
+// FP64) and the two sites next to the zipper centre are updated
+// variationally; full one-site variational sweeps refine the 2 chi MPS,
+// then a left-to-right SVD sweep truncates to chi.
 //
 // Diagram kernels (Fig. 7):
 //   site      out[l][a][j]  = sum_{x: P^L x = l} w(x) A[v'(x)] K[rho(x)] Xt[u(x)]
@@ -955,13 +957,60 @@ __global__ void copy_cols_kernel(const double* __restrict__ src, int64_t n, int 
 
 static unsigned blocks(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+// out[sigma'] = A[sigma] with the two-leg physical index re-split:
+// sigma = a' + da' b' (as stored) and sigma' = b' + db' a' (mirrored order).
+__global__ void swap_phys_kernel(const double* __restrict__ A, int da2, int db2, int64_t blk,
+                                 double* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(da2) * db2 * blk) return;
+  const int64_t sg = idx / blk, e = idx % blk;
+  const int64_t a2 = sg % da2, b2 = sg / da2;
+  out[(b2 + db2 * a2) * blk + e] = A[idx];
+}
+
+// out[sigma][i][g] = S[i] * site[sigma][i][g]
+__global__ void scale_mid_kernel(const double* __restrict__ site, const double* __restrict__ S, int ds, int t,
+                                 int Dg, double* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(ds) * t * Dg) return;
+  out[idx] = S[(idx / Dg) % t] * site[idx];
+}
+
+// The mediating geometry seen from the other side (rho <-> l, a' <-> b',
+// rho_d <-> l_d, W_h transposed): the apply kernels of the mirrored geometry
+// compute the left transfer of the original one.  The W_dr / W_dl views and
+// the upper split (da, db) are not read by those kernels.
+static RowGeom::Med mirror_med(const RowGeom::Med& m) {
+  RowGeom::Med r = m;
+  r.dR = m.dL;
+  r.dL = m.dR;
+  r.drd = m.dld;
+  r.dld = m.drd;
+  r.da2 = m.db2;
+  r.db2 = m.da2;
+  r.pos_h_rho = m.pos_h_ell;
+  r.pos_h_ell = m.pos_h_rho;
+  r.pos_d_rho = m.pos_d_ell;
+  r.pos_d_ell = m.pos_d_rho;
+  r.pos_a2 = m.pos_b2;
+  r.pos_b2 = m.pos_a2;
+  r.Wh_sp = m.Wh_sq;
+  r.Wh_sq = m.Wh_sp;
+  return r;
+}
+
 // -------------------------------------------------------------- the zipper
 struct Zipper {
   const tnb_clusters* cl;
   const tnb_env_opts& o;
   la::Scratch& ws;
   hipStream_t st;
-  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, conn, conn_next, connT, SVT, Yf, Cin, Cout;
+  DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, connT, SVT, Yf, Cin, Cout;
+  // variational refinement: mirrored operands, environments, SVD outputs
+  DevBuf<double> Pq, AT, AT2, LT, QU, Mw, Uw, Sw, VTw, L1, C1, Xc;
+  Site phiL;
+  std::vector<DevBuf<double>> cn;  // cn[k]: connector / right environment of the box at k-1 (cn[K] = 1)
+  std::vector<DevBuf<double>> Lv;  // left environments of the sweeps
 
   // Widest sketch block whose diagram tiles fit the LDS and register budget.
   static int block_width(int Da, int Db, int Dg, int s) {
@@ -977,12 +1026,12 @@ struct Zipper {
   // D X (or D^T X) over sketch blocks: every column is independent, so wide
   // sketches are processed in blocks that fit on chip.
   template <bool T>
-  void apply_cols(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
+  void apply_cols(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* X, int s,
                   double* out, int64_t n_in, int64_t n_out) {
     const int w = block_width(A.dl, A.dr, Dg, s);
     if (w >= s) {
-      if (T) applyT_block(g, k, A, Dg, dm, X, s, out);
-      else apply_block(g, k, A, Dg, dm, X, s, out);
+      if (T) applyT_block(g, k, A, Kc, Dg, dm, X, s, out);
+      else apply_block(g, k, A, Kc, Dg, dm, X, s, out);
       return;
     }
     ensure(Cin, size_t(n_in) * w);
@@ -991,8 +1040,8 @@ struct Zipper {
       const int wc = std::min(w, s - c0);
       hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(n_in * wc)), dim3(256), 0, st, X, n_in, s, c0, wc,
                          Cin.p, wc, 0);
-      if (T) applyT_block(g, k, A, Dg, dm, Cin.p, wc, Cout.p);
-      else apply_block(g, k, A, Dg, dm, Cin.p, wc, Cout.p);
+      if (T) applyT_block(g, k, A, Kc, Dg, dm, Cin.p, wc, Cout.p);
+      else apply_block(g, k, A, Kc, Dg, dm, Cin.p, wc, Cout.p);
       hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(n_out * wc)), dim3(256), 0, st, Cout.p, n_out, wc, 0, wc,
                          out, s, c0);
       HIPC(hipGetLastError());
@@ -1000,12 +1049,13 @@ struct Zipper {
   }
 
   // D X for site k of row geometry g; X: (ds*Dg) x s, out: (dm*Da) x s
-  void apply_block(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* X, int s,
+  void apply_block(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* X, int s,
                    double* out) {
     const int Da = A.dl, Db = A.dr;
     if (k % 2 == 0) {
       const auto& c = g.col[k / 2];
       // Xt[u] = sum_v W(v,u) X[v]: (du x Dg*s) = W^T (du x dv) . X (dv x Dg*s)
+      ensure(X1, size_t(c.du) * Dg * s);
       double* Xt = X1.p;
       la::gemm(1, c.du, Dg * s, c.dv, la::View{c.Wv, c.Wv_sq, c.Wv_sp, 0}, la::View{X, Dg * s, 1, 0},
                Xt, int64_t(Dg) * s, 0, 1.0, 0.0, ws, st);
@@ -1018,17 +1068,19 @@ struct Zipper {
                        double(c.dL) * Da * s + double(c.dL) * nfree));
       if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
         TNB_SITE_LAUNCH((s + 15) / 16, site_apply_mfma, dim3(c.dL), dim3(64), st, c.PL, FREE, nfree, c.PR, c.Bup,
-                        c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg, Xt, s, out);
+                        c.Bdn, c.w, A.data.p, Da, Db, Kc, Dg, Xt, s, out);
       } else {
         allow_big_lds(site_apply_kernel, size_t(Db) * s * sizeof(double));
         hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
                            k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
-                           conn.p, Dg, Xt, s, out);
+                           Kc, Dg, Xt, s, out);
       }
       HIPC(hipGetLastError());
         }
     } else {
       const auto& md = g.med[(k - 1) / 2];
+      ensure(X1, size_t(md.db) * md.dld * Dg * s);
+      ensure(X2, size_t(md.dld) * md.drd * Dg * s);
       // X1[b] (dld x Dg*s) = Wdr^T . X[b]  with X[(b*da + a)][Dg*s]
       la::gemm(md.db, md.dld, Dg * s, md.da, la::View{md.Wdr, md.Wdr_sq, md.Wdr_sp, 0},
                la::View{X, int64_t(Dg) * s, 1, int64_t(md.da) * Dg * s}, X1.p, int64_t(Dg) * s,
@@ -1053,13 +1105,13 @@ struct Zipper {
           // the kernel reads the connector as [l][g][b] (contiguous along b)
           const int64_t nconn = int64_t(md.dL) * Db * Dg;
           ensure(connT, size_t(nconn));
-          hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nconn)), dim3(256), 0, st, conn.p, int64_t(md.dL),
+          hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nconn)), dim3(256), 0, st, Kc, int64_t(md.dL),
                              Db, Dg, connT.p);
           const unsigned G = unsigned(md.drd * md.db2 * f.chR);
           hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0, st, f,
                              connT.p, X2.p, Da, Db, Dg, s, Yf.p);
         } else {
-          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, conn.p,
+          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, Kc,
                         X2.p, Da, Db, Dg, s, Yf.p);
         }
         HIPC(hipGetLastError());
@@ -1087,7 +1139,7 @@ struct Zipper {
   }
 
   // D^T Y; Y: (dm*Da) x s, out: (ds*Dg) x s
-  void applyT_block(const RowGeom& g, int k, const Site& A, int Dg, int dm, const double* Yin, int s,
+  void applyT_block(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* Yin, int s,
                     double* out) {
     const int Da = A.dl, Db = A.dr;
     if (k % 2 == 0) {
@@ -1095,6 +1147,7 @@ struct Zipper {
       const uint32_t full = c.k ? ((1u << c.k) - 1u) : 0u;
       const uint32_t FREE = full & ~c.Bup;
       const int nfree = 1 << popcount32(FREE);
+      ensure(X1, size_t(c.du) * Dg * s);
       double* G = X1.p;  // du x Dg x s
 {
       KTimer _t("site_applyT", st, 2.0 * s * Db * double(Dg + Da) * double(c.du) * nfree,
@@ -1102,11 +1155,11 @@ struct Zipper {
                        double(c.dL) * Da * s + double(c.du) * nfree));
       if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
         TNB_SITE_LAUNCH((s + 15) / 16, site_applyT_mfma, dim3(c.du), dim3(256), st, c.Bup, FREE, nfree, c.PL, c.PR,
-                        c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg, Yin, s, G);
+                        c.Bdn, c.w, A.data.p, Da, Db, Kc, Dg, Yin, s, G);
       } else {
         allow_big_lds(site_applyT_kernel, size_t(Db) * s * sizeof(double));
         hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
-                           k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, conn.p, Dg,
+                           k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, Kc, Dg,
                            Yin, s, G);
       }
       HIPC(hipGetLastError());
@@ -1116,6 +1169,8 @@ struct Zipper {
                out, int64_t(Dg) * s, 0, 1.0, 0.0, ws, st);
     } else {
       const auto& md = g.med[(k - 1) / 2];
+      ensure(X2, size_t(md.dld) * md.drd * Dg * s);
+      ensure(X1, size_t(md.dld) * md.db * Dg * s);
       double* G2 = X2.p;  // [ld][rd][Dg*s]
       MedF f;
       make_medf(md, &f);
@@ -1142,10 +1197,10 @@ struct Zipper {
                    8.0 * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
                           double(md.dld) * md.drd * Dg * s));
         if (Db <= 32) {
-          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, conn.p, Yf.p, Dg, Db,
+          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, Kc, Yf.p, Dg, Db,
                         0, s, G2);
         } else {
-          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, conn.p, Yf.p, Dg, Db,
+          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, Kc, Yf.p, Dg, Db,
                           0, s, G2);
         }
         HIPC(hipGetLastError());
@@ -1165,6 +1220,304 @@ struct Zipper {
     if (b.n < n) b.alloc(n + n / 4 + 64);
   }
 
+  // MPO bond on the left of the box at site k (rows of its matrix: [m][a]).
+  static int box_dm(const RowGeom& g, int k) { return k % 2 == 0 ? g.col[k / 2].dL : g.med[(k - 1) / 2].dR; }
+
+  // Thin SVD of a row-major n x m matrix keeping all m triplets (those below
+  // cut * sigma_max zeroed, with their vectors): U (n x m), Sv (m), Vt (m x m).
+  void svd_keep(const double* M, int64_t n, int m, double* U, double* Sv, double* Vt) {
+    la::thin_svd_tall(M, n, m, m, o.cut, U, Sv, Vt, ws, st);
+  }
+
+  // Left transfer through the box at site k (the environments of the overlap
+  // in Fig. 8d): Lin (rows_k x t, rows [m][a]) and the new site phi
+  // ([sigma][t][g]) give out (rows_{k+1} x g, rows [m'][b]):
+  //   site k = 2c:      out[rho][b] = sum_{x: P^R x = rho} w(x) A[v'(x)]^T L[P^L x] Pt[u(x)],
+  //                     Pt[u] = sum_v W_v(v, u) phi[v]
+  //   mediating k:      out[l][b] = sum_rho W_h(rho, l) A[a'(rho) + da' b'(l)]^T L[rho] P2[rho_d(rho)][l_d(l)],
+  //                     P2[rd][ld] = sum_{alpha, beta} W_dr(alpha, ld) W_dl(beta, rd) phi[alpha + da beta]
+  // The site form is the site diagram with the roles of the P^L and P^R
+  // projections exchanged; the mediating form is the factored mediating
+  // diagram of the mirrored geometry (rho <-> l, a' <-> b', rho_d <-> l_d),
+  // so both run on the same kernels as the apply.
+  void left_cols(const RowGeom& g, int k, const Site& A, const double* Lin, int t, const Site& phi,
+                 double* out) {
+    const int Da = A.dl, Db = A.dr, gc = phi.dr;
+    const int64_t tg = int64_t(t) * gc;
+    int64_t n_q, dout;  // rows of the prepared operand (x gc columns); output blocks
+    if (k % 2 == 0) {
+      const auto& c = g.col[k / 2];
+      n_q = int64_t(c.du) * t;
+      dout = c.dR;
+      ensure(Pq, size_t(std::max<int64_t>(n_q * gc, 1)));
+      la::gemm(1, c.du, int(tg), c.dv, la::View{c.Wv, c.Wv_sq, c.Wv_sp, 0}, la::View{phi.data.p, tg, 1, 0}, Pq.p,
+               tg, 0, 1.0, 0.0, ws, st);
+      const int64_t na = int64_t(A.size());
+      ensure(AT, size_t(na));
+      hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(na)), dim3(256), 0, st, A.data.p, int64_t(A.d), Da, Db,
+                         AT.p);
+    } else {
+      const auto& md = g.med[(k - 1) / 2];
+      n_q = int64_t(md.drd) * md.dld * t;
+      dout = md.dL;
+      ensure(X1, size_t(md.db) * md.dld * tg);
+      ensure(Pq, size_t(std::max<int64_t>(n_q * gc, 1)));
+      // X1[beta] (dld x t g) = W_dr^T . phi[beta]   (phi rows alpha + da beta)
+      la::gemm(md.db, md.dld, int(tg), md.da, la::View{md.Wdr, md.Wdr_sq, md.Wdr_sp, 0},
+               la::View{phi.data.p, tg, 1, int64_t(md.da) * tg}, X1.p, tg, int64_t(md.dld) * tg, 1.0, 0.0, ws, st);
+      // P2[rd][ld] = W_dl^T . X1[:, ld]
+      la::gemm(md.dld, md.drd, int(tg), md.db, la::View{md.Wdl, md.Wdl_sq, md.Wdl_sp, 0},
+               la::View{X1.p, int64_t(md.dld) * tg, 1, tg}, Pq.p, int64_t(md.dld) * tg, tg, 1.0, 0.0, ws, st);
+      // L transposed per rho ([rho][t][a]) and the site with its physical
+      // index split exchanged (sigma' = b' + db' a')
+      const int64_t nl = int64_t(md.dR) * Da * t;
+      ensure(LT, size_t(nl));
+      hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nl)), dim3(256), 0, st, Lin, int64_t(md.dR), Da, t,
+                         LT.p);
+      const int64_t na = int64_t(A.size());
+      ensure(AT, size_t(na));
+      hipLaunchKernelGGL(swap_phys_kernel, dim3(blocks(na)), dim3(256), 0, st, A.data.p, md.da2, md.db2,
+                         int64_t(Da) * Db, AT.p);
+      if (Da > 32) {  // the generic accumulation kernel reads [sigma'][b][a]
+        ensure(AT2, size_t(na));
+        hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(na)), dim3(256), 0, st, AT.p, int64_t(A.d), Da, Db,
+                           AT2.p);
+      }
+      HIPC(hipGetLastError());
+    }
+    const int w = block_width(Db, Da, t, gc);
+    if (w >= gc) {
+      left_block(g, k, A, Lin, t, Pq.p, gc, out);
+      return;
+    }
+    ensure(Cin, size_t(n_q) * w);
+    ensure(Cout, size_t(dout) * Db * w);
+    for (int c0 = 0; c0 < gc; c0 += w) {
+      const int wc = std::min(w, gc - c0);
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(n_q * wc)), dim3(256), 0, st, Pq.p, n_q, gc, c0, wc, Cin.p,
+                         wc, 0);
+      left_block(g, k, A, Lin, t, Cin.p, wc, Cout.p);
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(dout * Db * wc)), dim3(256), 0, st, Cout.p, dout * Db, wc, 0,
+                         wc, out, gc, c0);
+      HIPC(hipGetLastError());
+    }
+  }
+
+  // One column block of left_cols; Q is the prepared operand (Pt or P2, s columns).
+  void left_block(const RowGeom& g, int k, const Site& A, const double* Lin, int t, const double* Q, int s,
+                  double* out) {
+    const int Da = A.dl, Db = A.dr;
+    if (k % 2 == 0) {
+      const auto& c = g.col[k / 2];
+      const uint32_t full = c.k ? ((c.k == 32) ? ~0u : ((1u << c.k) - 1u)) : 0u;
+      const uint32_t FREE = full & ~c.PR;
+      const int nfree = 1 << popcount32(FREE);
+      KTimer _t("site_left", st, 2.0 * s * Da * double(t + Db) * double(c.dR) * nfree,
+                8.0 * (double(c.dvd) * Da * Db + double(c.dL) * Da * t + double(c.du) * t * s +
+                       double(c.dR) * Db * s + double(c.dR) * nfree));
+      // the site chain with P^L and P^R exchanged: A^T (Db x Da), L[l] (Da x t), Pt[u] (t x s)
+      if (Db <= 16 && Da <= 16 && t <= 32 && s <= 64) {
+        TNB_SITE_LAUNCH((s + 15) / 16, site_apply_mfma, dim3(c.dR), dim3(64), st, c.PR, FREE, nfree, c.PL, c.Bup,
+                        c.Bdn, c.w, AT.p, Db, Da, Lin, t, Q, s, out);
+      } else {
+        allow_big_lds(site_apply_kernel, size_t(Da) * s * sizeof(double));
+        hipLaunchKernelGGL(site_apply_kernel, dim3(c.dR), dim3(256), size_t(Da) * s * sizeof(double), st, k, c.PR,
+                           FREE, nfree, c.PL, c.Bup, c.Bdn, c.w, AT.p, Db, Da, Lin, t, Q, s, out);
+      }
+      HIPC(hipGetLastError());
+    } else {
+      MedF f;
+      make_medf(mirror_med(g.med[(k - 1) / 2]), &f);
+      const auto& mm = f.md;  // mirrored: "rho" is l, "l" is rho
+      ensure(Yf, size_t(mm.drd) * mm.db2 * f.nHR * Da * s);
+      const int nj = (s + 15) / 16;
+      {
+        KTimer _t1("medf_lbin", st, double(mm.drd) * mm.dL * (2.0 * Da * t * s + 2.0 * f.nHR * Da * s),
+                   8.0 * (double(mm.dL) * Da * t + double(mm.dld) * mm.drd * t * s +
+                          double(mm.drd) * mm.db2 * f.nHR * Da * s));
+        if (t <= 32) {
+          const unsigned G = unsigned(mm.drd * mm.db2 * f.chR);
+          hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3((G + 7) / 8 * 8 * nj, (Da + 15) / 16), dim3(256), 0, st, f,
+                             LT.p, Q, Db, Da, t, s, Yf.p);
+        } else {
+          const size_t shm = medf_bin_lds(t, nj);
+          check_lds(shm);
+          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(mm.drd * mm.db2 * f.chR, (Da + 15) / 16), shm, st, f, Lin, Q,
+                        Db, Da, t, s, Yf.p);
+        }
+        HIPC(hipGetLastError());
+      }
+      {
+        KTimer _t2("medf_lacc", st, double(mm.dR) * mm.db2 * 2.0 * Db * Da * s,
+                   8.0 * (double(mm.da2) * mm.db2 * Da * Db + double(mm.drd) * mm.db2 * f.nHR * Da * s +
+                          double(mm.dR) * Db * s));
+        if (Da <= 32) {
+          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(mm.dR, (Db + 15) / 16), 0, st, f, AT.p, Yf.p, Db, Da, 0, s, out);
+        } else {
+          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 1, dim3(mm.dR, (Db + 15) / 16), 0, st, f, AT2.p, Yf.p, Db, Da, 0, s,
+                        out);
+        }
+        HIPC(hipGetLastError());
+      }
+    }
+  }
+
+  // Site phi ([sigma][t][g]) as the column block X (sigma g x t) of a box.
+  void site_cols(const Site& phi, double* X) {
+    const int64_t n = int64_t(phi.size());
+    hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(n)), dim3(256), 0, st, phi.data.p, int64_t(phi.d),
+                       phi.dl, phi.dr, X);
+    HIPC(hipGetLastError());
+  }
+
+  // New site ([sigma][t][g]) from a column block V (sigma g x t).
+  void cols_site(const double* V, Site& phi) {
+    hipLaunchKernelGGL(vb_to_site_kernel, dim3(blocks(int64_t(phi.size()))), dim3(256), 0, st, V, phi.d, phi.dr,
+                       phi.dl, phi.data.p);
+    HIPC(hipGetLastError());
+  }
+
+  static void alloc_site(Site& s, int dl, int d, int dr) {
+    s.dl = dl;
+    s.d = d;
+    s.dr = dr;
+    if (s.data.n < s.size()) s.data.alloc(s.size());
+  }
+
+  // Variational sweep over sites k and k+1 after zipper step k (Fig. 8d).
+  // The rows of the box at k are taken as an orthonormal basis (as in the
+  // zipper's own SVD), in which the state is QU . (S Vt) . site k+1 ...:
+  //  1. centre moved to k+1: the left-canonical factor phiL of S Vt and QU
+  //     give the left environment L1; site k+1 becomes the transposed box at
+  //     k+1 applied to L1, made right-canonical, and its connector is rebuilt;
+  //  2. site k is updated within the span of QU: the transposed box at k
+  //     applied to QU, split into a right-canonical site and the connector
+  //     QU . (V S).
+  // Each update maximises the overlap with the target over one site with the
+  // others held fixed.
+  void window(const RowGeom& g, const std::vector<int>& dims, int k, const Mps& below, Mps& outm, int s, int t,
+              int64_t rows0) {
+    const Site& A0 = below.sites[k];
+    const Site& A1 = below.sites[k + 1];
+    Site& s0 = outm.sites[k];
+    Site& s1 = outm.sites[k + 1];
+    const int ds = dims[k], Dg = s0.dr, ds1 = dims[k + 1], Dg1 = s1.dr;
+    const int dm0 = box_dm(g, k), dm1 = box_dm(g, k + 1);
+    const int64_t rows1 = int64_t(dm1) * A1.dl, cols0 = int64_t(ds) * Dg, cols1 = int64_t(ds1) * Dg1;
+    // QU = Q . VT^T (rows0 x t): orthonormal columns
+    ensure(QU, size_t(rows0) * t);
+    la::gemm(1, int(rows0), t, s, la::View{Qb.p, s, 1, 0}, la::View{VT.p, 1, s, 0}, QU.p, t, 0, 1.0, 0.0, ws, st);
+    // S Vt with rows (sigma, i): site k scaled by S[i]; its left-canonical factor
+    const int64_t n0 = int64_t(ds) * t;
+    ensure(Mw, size_t(n0) * Dg);
+    hipLaunchKernelGGL(scale_mid_kernel, dim3(blocks(n0 * Dg)), dim3(256), 0, st, s0.data.p, S.p, ds, t, Dg, Mw.p);
+    ensure(Uw, size_t(std::max<int64_t>(n0 * Dg, std::max(cols1, cols0) * std::max(Dg, t))));
+    ensure(Sw, size_t(std::max(Dg, t)));
+    ensure(VTw, size_t(std::max(Dg, t)) * std::max(Dg, t));
+    svd_keep(Mw.p, n0, Dg, Uw.p, Sw.p, VTw.p);
+    alloc_site(phiL, t, ds, Dg);
+    HIPC(hipMemcpyAsync(phiL.data.p, Uw.p, phiL.size() * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // L1 (rows1 x Dg) and the update of site k+1
+    ensure(L1, size_t(rows1) * Dg);
+    left_cols(g, k, A0, QU.p, t, phiL, L1.p);
+    ensure(C1, size_t(cols1) * Dg);
+    apply_cols<true>(g, k + 1, A1, cn[k + 2].p, Dg1, dm1, L1.p, Dg, C1.p, rows1, cols1);
+    svd_keep(C1.p, cols1, Dg, Uw.p, Sw.p, VTw.p);
+    cols_site(Uw.p, s1);
+    ensure(cn[k + 1], size_t(rows1) * Dg);
+    apply_cols<false>(g, k + 1, A1, cn[k + 2].p, Dg1, dm1, Uw.p, Dg, cn[k + 1].p, cols1, rows1);
+    // update of site k within span(QU)
+    ensure(C1, size_t(cols0) * t);
+    apply_cols<true>(g, k, A0, cn[k + 1].p, Dg, dm0, QU.p, t, C1.p, rows0, cols0);
+    svd_keep(C1.p, cols0, t, Uw.p, Sw.p, VTw.p);
+    cols_site(Uw.p, s0);
+    ensure(Wc, size_t(t) * t);
+    hipLaunchKernelGGL(scale_vt_kernel, dim3(blocks(int64_t(t) * t)), dim3(256), 0, st, VTw.p, Sw.p, t, t, Wc.p);
+    ensure(cn[k], size_t(rows0) * t);
+    la::gemm(1, int(rows0), t, t, la::View{QU.p, t, 1, 0}, la::View{Wc.p, t, 1, 0}, cn[k].p, t, 0, 1.0, 0.0, ws, st);
+    HIPC(hipGetLastError());
+  }
+
+  // One-site variational sweeps of the finished MPS towards T_r Psi_{r+1}
+  // (Fig. 8d): the centre visits 0 .. K-1 .. 0, then 1 .. K-1 .. 0 for each
+  // further sweep.  At each visit the centre becomes the transposed box
+  // applied to its left environment (the overlap maximiser over that site);
+  // moving on, it is split by an SVD into a canonical site and a factor
+  // carried to the neighbour, and the environment on the side it leaves is
+  // extended.  Ends with the norm in site 0 and the other sites
+  // right-canonical.  Right environments are kept in cn[], left ones in Lv[].
+  void sweeps(const RowGeom& g, const std::vector<int>& dims, const Mps& below, Mps& outm, int n_sweeps) {
+    const int K = int(outm.sites.size());
+    for (int k = K - 1; k >= 1; --k) {
+      const Site& A = below.sites[k];
+      const Site& p = outm.sites[k];
+      const int dm = box_dm(g, k);
+      const int64_t rows = int64_t(dm) * A.dl, cols = int64_t(dims[k]) * p.dr;
+      ensure(Xc, size_t(cols) * p.dl);
+      site_cols(p, Xc.p);
+      ensure(cn[k], size_t(rows) * p.dl);
+      apply_cols<false>(g, k, A, cn[k + 1].p, p.dr, dm, Xc.p, p.dl, cn[k].p, cols, rows);
+    }
+    if (int(Lv.size()) < K) Lv.resize(K);
+    ensure(Lv[0], 1);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, Lv[0].p, int64_t(1), 1.0);
+    std::vector<int> seq;
+    for (int k = 0; k < K; ++k) seq.push_back(k);
+    for (int k = K - 2; k >= 0; --k) seq.push_back(k);
+    for (int sw = 1; sw < n_sweeps; ++sw) {
+      for (int k = 1; k < K; ++k) seq.push_back(k);
+      for (int k = K - 2; k >= 0; --k) seq.push_back(k);
+    }
+    for (size_t i = 0; i < seq.size(); ++i) {
+      const int k = seq[i];
+      const Site& A = below.sites[k];
+      Site& p = outm.sites[k];
+      const int t = p.dl, Dg = p.dr, ds = dims[k], dm = box_dm(g, k);
+      const int64_t rows = int64_t(dm) * A.dl, cols = int64_t(ds) * Dg;
+      ensure(C1, size_t(cols) * t);
+      apply_cols<true>(g, k, A, cn[k + 1].p, Dg, dm, Lv[k].p, t, C1.p, rows, cols);
+      const bool last = i + 1 == seq.size();
+      const int nxt = last ? k : seq[i + 1];  // the last visit moves nowhere
+      if (!last && nxt == k + 1) {
+        cols_site(C1.p, p);
+        const int64_t n = int64_t(ds) * t;
+        ensure(Uw, size_t(n) * Dg);
+        ensure(Sw, size_t(Dg));
+        ensure(VTw, size_t(Dg) * Dg);
+        svd_keep(p.data.p, n, Dg, Uw.p, Sw.p, VTw.p);  // rows (sigma, i)
+        HIPC(hipMemcpyAsync(p.data.p, Uw.p, p.size() * sizeof(double), hipMemcpyDeviceToDevice, st));
+        Site& q = outm.sites[k + 1];
+        ensure(SVT, size_t(Dg) * Dg);
+        hipLaunchKernelGGL(scale_rows_kernel, dim3(blocks(int64_t(Dg) * Dg)), dim3(256), 0, st, VTw.p, Sw.p, Dg, Dg,
+                           SVT.p);
+        ensure(Mw, q.size());
+        la::gemm(q.d, Dg, q.dr, q.dl, la::View{SVT.p, Dg, 1, 0}, la::View{q.data.p, q.dr, 1, int64_t(q.dl) * q.dr},
+                 Mw.p, q.dr, int64_t(Dg) * q.dr, 1.0, 0.0, ws, st);
+        HIPC(hipMemcpyAsync(q.data.p, Mw.p, q.size() * sizeof(double), hipMemcpyDeviceToDevice, st));
+        const int64_t rows_n = int64_t(box_dm(g, k + 1)) * A.dr;
+        ensure(Lv[k + 1], size_t(rows_n) * Dg);
+        left_cols(g, k, A, Lv[k].p, t, p, Lv[k + 1].p);
+      } else if (!last && nxt == k - 1) {
+        ensure(Uw, size_t(cols) * t);
+        ensure(Sw, size_t(t));
+        ensure(VTw, size_t(t) * t);
+        svd_keep(C1.p, cols, t, Uw.p, Sw.p, VTw.p);
+        cols_site(Uw.p, p);
+        Site& q = outm.sites[k - 1];
+        ensure(Wc, size_t(t) * t);
+        hipLaunchKernelGGL(scale_vt_kernel, dim3(blocks(int64_t(t) * t)), dim3(256), 0, st, VTw.p, Sw.p, t, t, Wc.p);
+        ensure(Mw, q.size());
+        la::gemm(q.d, q.dl, t, t, la::View{q.data.p, t, 1, int64_t(q.dl) * t}, la::View{Wc.p, t, 1, 0}, Mw.p, t,
+                 int64_t(q.dl) * t, 1.0, 0.0, ws, st);
+        HIPC(hipMemcpyAsync(q.data.p, Mw.p, q.size() * sizeof(double), hipMemcpyDeviceToDevice, st));
+        apply_cols<false>(g, k, A, cn[k + 1].p, Dg, dm, Uw.p, t, cn[k].p, cols, rows);
+      } else {
+        cols_site(C1.p, p);
+      }
+      HIPC(hipGetLastError());
+    }
+  }
+
   // compress(T_r psi) -> out (2C-1 sites), returns log of the factored norm
   double run(int r, const Mps& below, Mps& outm, bool truncate) {
     const RowGeom g = row_geom(cl, r);
@@ -1174,16 +1527,16 @@ struct Zipper {
     const int width = 2 * chi + o.sketch_extra;
     outm.sites.clear();
     outm.sites.resize(K);
-    ensure(conn, 1);
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, conn.p, int64_t(1), 1.0);
-    int Dg = 1, dmk = 1;  // right bond of the new MPS, MPO bond right of site k
+    if (int(cn.size()) < K + 1) cn.resize(K + 1);
+    ensure(cn[K], 1);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, cn[K].p, int64_t(1), 1.0);
+    const bool windows = truncate && o.var_window >= 2;
+    int Dg = 1;  // right bond of the new MPS at site k
     for (int k = K - 1; k >= 0; --k) {
       const Site& A = below.sites[k];
       const int Da = A.dl;
-      int dm;
-      if (k % 2 == 0) dm = g.col[k / 2].dL;
-      else dm = g.med[(k - 1) / 2].dR;
-      (void)dmk;
+      const int dm = box_dm(g, k);
+      const double* Kc = cn[k + 1].p;
       const int ds = dims[k];
       const int64_t n_rows = int64_t(dm) * Da, n_cols = int64_t(ds) * Dg;
       const int t = int(std::min<int64_t>({int64_t(2) * chi, n_rows, n_cols}));
@@ -1212,46 +1565,49 @@ struct Zipper {
       } else {
         hipLaunchKernelGGL(identity_kernel, dim3(blocks(n_cols * n_cols)), dim3(256), 0, st, Om.p, n_cols);
       }
-      apply_cols<false>(g, k, A, Dg, dm, Om.p, s, Y.p, n_cols, n_rows);
+      apply_cols<false>(g, k, A, Kc, Dg, dm, Om.p, s, Y.p, n_cols, n_rows);
       if (sketch) {
         for (int it = 0; it < o.power_iters; ++it) {
           la::orth(Y.p, n_rows, s, o.cut, Qb.p, ws, st);
-          apply_cols<true>(g, k, A, Dg, dm, Qb.p, s, Z.p, n_rows, n_cols);
+          apply_cols<true>(g, k, A, Kc, Dg, dm, Qb.p, s, Z.p, n_rows, n_cols);
           la::orth(Z.p, n_cols, s, o.cut, Qb.p, ws, st);
-          apply_cols<false>(g, k, A, Dg, dm, Qb.p, s, Y.p, n_cols, n_rows);
+          apply_cols<false>(g, k, A, Kc, Dg, dm, Qb.p, s, Y.p, n_cols, n_rows);
         }
       }
       la::orth(Y.p, n_rows, s, o.cut, Qb.p, ws, st);
-      apply_cols<true>(g, k, A, Dg, dm, Qb.p, s, Bt.p, n_rows, n_cols);
+      apply_cols<true>(g, k, A, Kc, Dg, dm, Qb.p, s, Bt.p, n_rows, n_cols);
       // B = Bt^T (s x n_cols): thin SVD through Bt (n_cols x s)
       ensure(Vb, size_t(n_cols) * t);
       ensure(S, size_t(t));
       ensure(VT, size_t(t) * s);
       la::thin_svd_tall(Bt.p, n_cols, s, t, o.cut, Vb.p, S.p, VT.p, ws, st);
       Site& ns = outm.sites[k];
-      ns.dl = t;
-      ns.d = ds;
-      ns.dr = Dg;
-      ns.data.alloc(ns.size());
-      hipLaunchKernelGGL(vb_to_site_kernel, dim3(blocks(int64_t(ds) * Dg * t)), dim3(256), 0, st, Vb.p,
-                         ds, Dg, t, ns.data.p);
-      // connector (dm*Da x t) = Q (n_rows x s) . (U_B S) (s x t)
-      ensure(Wc, size_t(s) * t);
-      hipLaunchKernelGGL(scale_vt_kernel, dim3(blocks(int64_t(s) * t)), dim3(256), 0, st, VT.p, S.p, s, t, Wc.p);
-      ensure(conn_next, size_t(n_rows) * t);
-      la::gemm(1, int(n_rows), t, s, la::View{Qb.p, s, 1, 0}, la::View{Wc.p, t, 1, 0}, conn_next.p, t, 0,
-               1.0, 0.0, ws, st);
-      std::swap(conn, conn_next);
+      alloc_site(ns, t, ds, Dg);
+      cols_site(Vb.p, ns);
+      if (windows && k + 1 < K) {
+        window(g, dims, k, below, outm, s, t, n_rows);
+      } else {
+        // connector (dm*Da x t) = Q (n_rows x s) . (U_B S) (s x t)
+        ensure(Wc, size_t(s) * t);
+        hipLaunchKernelGGL(scale_vt_kernel, dim3(blocks(int64_t(s) * t)), dim3(256), 0, st, VT.p, S.p, s, t, Wc.p);
+        ensure(cn[k], size_t(n_rows) * t);
+        la::gemm(1, int(n_rows), t, s, la::View{Qb.p, s, 1, 0}, la::View{Wc.p, t, 1, 0}, cn[k].p, t, 0, 1.0, 0.0,
+                 ws, st);
+      }
       Dg = t;
-      dmk = dm;
       HIPC(hipGetLastError());
     }
-    // conn is 1x1: the factored scalar
+    // cn[0] is 1x1: the factored scalar
     double scalar = 0.0;
-    HIPC(hipMemcpyAsync(&scalar, conn.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(&scalar, cn[0].p, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     if (!std::isfinite(scalar)) fail(TNB_ENUMERIC, "non-finite value in the row transfer of row " + std::to_string(r));
     if (scalar == 0.0) fail(TNB_ENUMERIC, "row transfer of row " + std::to_string(r) + " vanished");
+    if (truncate && o.var_sweeps > 0) {
+      // the first visit of the sweeps replaces site 0, so the scalar drops out
+      sweeps(g, dims, below, outm, o.var_sweeps);
+      return sweep(outm);
+    }
     if (scalar < 0.0)
       hipLaunchKernelGGL(scale_kernel, dim3(blocks(int64_t(outm.sites[0].size()))), dim3(256), 0, st,
                          outm.sites[0].data.p, int64_t(outm.sites[0].size()), -1.0);
@@ -1259,7 +1615,6 @@ struct Zipper {
     if (truncate) logn += sweep(outm);
     return logn;
   }
-
   static uint64_t splitmix64_host(uint64_t c) {
     uint64_t z = (c + 1ull) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -1313,7 +1668,6 @@ struct Zipper {
     return std::log(nrm);
   }
 };
-
 }  // namespace tnb
 
 using namespace tnb;
@@ -1325,8 +1679,10 @@ extern "C" tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opt
     *out = nullptr;
     if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
     if (!opts || opts->chi < 1 || opts->chi > 64 || opts->sketch_extra < 0 || opts->sketch_extra > 64 ||
-        opts->power_iters < 0 || opts->power_iters > 8 || !(opts->cut >= 1e-7) || !(opts->cut < 1.0))
-      fail(TNB_EINVAL, "options out of range (1 <= chi <= 64, 0 <= extra <= 64, 0 <= power <= 8, 1e-7 <= cut < 1)");
+        opts->power_iters < 0 || opts->power_iters > 8 || !(opts->cut >= 1e-7) || !(opts->cut < 1.0) ||
+        (opts->var_window != 0 && opts->var_window != 2) || opts->var_sweeps < 0 || opts->var_sweeps > 8)
+      fail(TNB_EINVAL, "options out of range (1 <= chi <= 64, 0 <= extra <= 64, 0 <= power <= 8, 1e-7 <= cut < 1, "
+                       "var_window 0 or 2, 0 <= var_sweeps <= 8)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     auto env = std::make_unique<tnb_env>();
     env->cl = cl;
@@ -1385,5 +1741,92 @@ extern "C" tnb_status tnb_env_site_shape(const tnb_env* env, int32_t r, int32_t 
     if (dl) *dl = m.sites[k].dl;
     if (d) *d = m.sites[k].d;
     if (dr) *dr = m.sites[k].dr;
+  });
+}
+
+// ------------------------------------------------- single-diagram entry points
+namespace {
+
+// Device tensor borrowed as an MPS site for the duration of a call (the
+// Site's buffer is released without freeing it).
+struct BorrowedSite {
+  Site s;
+  BorrowedSite(const double* p, int dl, int d, int dr) {
+    s.dl = dl;
+    s.d = d;
+    s.dr = dr;
+    s.data.p = const_cast<double*>(p);
+    s.data.n = s.size();
+  }
+  ~BorrowedSite() {
+    s.data.p = nullptr;
+    s.data.n = 0;
+  }
+};
+
+struct DiagDims {
+  int dm_in, dm_out, ds, ds_below;
+};
+
+DiagDims diagram_dims(const tnb_clusters* cl, int r, int k) {
+  if (r < 0 || r >= cl->lat.R) fail(TNB_EINVAL, "row out of range");
+  const RowGeom g = row_geom(cl, r);
+  const std::vector<int> dims = phys_dims(cl, r);
+  const std::vector<int> below = phys_dims(cl, r + 1);
+  if (k < 0 || k >= int(dims.size())) fail(TNB_EINVAL, "site index out of range");
+  DiagDims d;
+  d.dm_in = Zipper::box_dm(g, k);
+  d.dm_out = k % 2 == 0 ? g.col[k / 2].dR : g.med[(k - 1) / 2].dL;
+  d.ds = dims[k];
+  d.ds_below = below[k];
+  return d;
+}
+
+}  // namespace
+
+extern "C" tnb_status tnb_diagram_dims(const tnb_clusters* cl, int32_t r, int32_t k, int32_t* dm_in,
+                                       int32_t* dm_out, int32_t* ds, int32_t* ds_below) {
+  return guarded([&] {
+    if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
+    const DiagDims d = diagram_dims(cl, r, k);
+    if (dm_in) *dm_in = d.dm_in;
+    if (dm_out) *dm_out = d.dm_out;
+    if (ds) *ds = d.ds;
+    if (ds_below) *ds_below = d.ds_below;
+  });
+}
+
+extern "C" tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32_t mode,
+                                        const double* d_A, int32_t Da, int32_t Db, const double* d_K, int32_t Dg,
+                                        const double* d_X, int32_t s, double* d_out, int64_t out_len,
+                                        tnb_stream stream) {
+  return guarded([&] {
+    if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
+    if (mode < 0 || mode > 2) fail(TNB_EINVAL, "mode must be 0 (apply), 1 (transpose) or 2 (left transfer)");
+    if (Da < 1 || Db < 1 || Dg < 1 || s < 1 || Da > 128 || Db > 128 || Dg > 128 || s > 256)
+      fail(TNB_EINVAL, "bond dimensions out of range (1 .. 128; s 1 .. 256)");
+    if (!d_A || !d_K || !d_X || !d_out) fail(TNB_EINVAL, "NULL tensor");
+    const DiagDims dd = diagram_dims(cl, r, k);
+    const int64_t rows = int64_t(dd.dm_in) * Da, cols = int64_t(dd.ds) * Dg;
+    const int64_t need = mode == 0 ? rows * s : mode == 1 ? cols * s : int64_t(dd.dm_out) * Db * s;
+    if (out_len < need) fail(TNB_EINVAL, "output too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    tnb_env_opts o{};
+    o.chi = 1;
+    o.cut = 1e-7;
+    la::Scratch ws;
+    Zipper z{cl, o, ws, st};
+    const RowGeom g = row_geom(cl, r);
+    BorrowedSite A(d_A, Da, dd.ds_below, Db);
+    if (mode == 0) {
+      z.apply_cols<false>(g, k, A.s, d_K, Dg, dd.dm_in, d_X, s, d_out, cols, rows);
+    } else if (mode == 1) {
+      z.apply_cols<true>(g, k, A.s, d_K, Dg, dd.dm_in, d_X, s, d_out, rows, cols);
+    } else {
+      BorrowedSite phi(d_X, Dg, dd.ds, s);
+      z.left_cols(g, k, A.s, d_K, Dg, phi.s, d_out);
+    }
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(st));  // the scratch is freed on return
   });
 }

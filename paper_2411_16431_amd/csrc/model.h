@@ -27,6 +27,9 @@ struct tnb_clusters {
   std::map<int64_t, int> bond_of;  // m*cells + n (m < n) -> index
   tnb::DevBuf<double> E_bond, W_bond;
   double shift = 0.0;  // sum over all tables of -beta * min energy
+  // the instance on the device (energies of returned states, Eq. 1)
+  tnb::DevBuf<int32_t> d_ei, d_ej;
+  tnb::DevBuf<double> d_J, d_h;
 
   uint32_t B(int m, int n) const {
     if (m < 0 || n < 0) return 0;

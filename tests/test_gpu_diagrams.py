@@ -1,0 +1,166 @@
+"""Parity of single diagram applications (Fig. 7, Fig. 8c-d) with the oracle
+at the full size of the benchmark workload: Zephyr Z_2 (t = 4, 16-spin cells,
+d = 2^16), row 1, the site diagram of column 1 (x over 2^16 values) and the
+central mediating diagram (legs 65536 x 65536), in the launch shape the
+zipper uses there (bond of Psi_{r+1} 16, new bond 32, sketch width 40).
+
+The caller-side tensors are seeded normal draws; both sides receive the same
+arrays.  Outputs the oracle can afford one by one (rows rho of the mediating
+apply, columns l of its left transfer) are sampled, including the first and
+last index and class boundaries; the transpose of the mediating diagram, whose
+oracle form has no row restriction, is checked by the adjoint identity
+<Y, D X> = <D^T Y, X>, which holds at any size."""
+import numpy as np
+import pytest
+
+from tnb_inputs import make_instance
+from oracle.bmps import Network, RowOps
+
+pytestmark = pytest.mark.gpu
+
+R_ROW, K_SITE, K_MED = 1, 2, 3
+CHI_B, DG, S = 16, 32, 40
+TOL = 1e-12
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_16431_amd as pk
+    return pk, torch
+
+
+@pytest.fixture(scope="module")
+def setup():
+    pk, torch = _gpu()
+    inst = make_instance("zephyr", 1000, jdist="uniform", hdist="uniform0.1", m=2, t=4)
+    net = Network(inst, 1.0)
+    cl = pk.Clusters(inst, 1.0)
+    return pk, torch, inst, net, cl
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _close(got, ref, what):
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max()
+    assert scale > 0
+    assert err <= TOL * scale, "%s: max |diff| %.3e vs max |ref| %.3e" % (what, err, scale)
+
+
+def _sample(n, picks):
+    """Indices picks (negative: from the end) plus one seeded random index."""
+    idx = {p % n for p in picks}
+    idx.add(int(np.random.default_rng(n).integers(0, n)))
+    return np.array(sorted(idx))
+
+
+def test_full_size_dims(setup):
+    pk, torch, inst, net, cl = setup
+    assert pk.diagram_dims(cl, R_ROW, K_SITE) == (4096, 65536, 256, 256)
+    assert pk.diagram_dims(cl, R_ROW, K_MED) == (65536, 65536, 256, 65536)
+
+
+def test_site_diagram_full_size(setup):
+    pk, torch, inst, net, cl = setup
+    c = K_SITE // 2
+    ops = RowOps(net, R_ROW)
+    dm_in, dm_out, ds, dsb = pk.diagram_dims(cl, R_ROW, K_SITE)
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((dsb, CHI_B, CHI_B))          # [sigma][a][b]
+    Kc = rng.standard_normal((dm_out, CHI_B, DG))         # [rho][b][g]
+    X = rng.standard_normal((ds, DG, S))                  # [v][g][j]
+    Y = rng.standard_normal((dm_in, CHI_B, S))            # [l][a][j]
+    got = pk.diagram_apply(cl, R_ROW, K_SITE, 0, _dev(torch, A), _dev(torch, Kc), _dev(torch, X)).cpu().numpy()
+    ref = ops.site_apply(c, A.transpose(1, 0, 2), Kc.transpose(1, 0, 2), X).transpose(1, 0, 2)
+    _close(got, ref, "site apply")
+    got = pk.diagram_apply(cl, R_ROW, K_SITE, 1, _dev(torch, A), _dev(torch, Kc), _dev(torch, Y)).cpu().numpy()
+    ref = ops.site_applyT(c, A.transpose(1, 0, 2), Kc.transpose(1, 0, 2), Y.transpose(1, 0, 2))
+    _close(got, ref, "site transpose")
+    # left transfer: L [l][a][t] with t = DG, new site phi [v][t][g] with g = DG
+    L = rng.standard_normal((dm_in, CHI_B, DG))
+    phi = rng.standard_normal((ds, DG, DG))
+    got = pk.diagram_apply(cl, R_ROW, K_SITE, 2, _dev(torch, A), _dev(torch, L), _dev(torch, phi)).cpu().numpy()
+    ref = ops.site_left(c, A.transpose(1, 0, 2), L.transpose(1, 0, 2), phi.transpose(1, 0, 2)).transpose(1, 0, 2)
+    _close(got, ref, "site left transfer")
+
+
+def test_mediating_diagram_full_size(setup):
+    pk, torch, inst, net, cl = setup
+    c = (K_MED - 1) // 2
+    ops = RowOps(net, R_ROW)
+    M = ops.med[c]
+    dm_in, dm_out, ds, dsb = pk.diagram_dims(cl, R_ROW, K_MED)
+    da, db = net.phys_dims(R_ROW)[1][K_MED]
+    assert (M["dR"], M["dL"], da * db) == (dm_in, dm_out, ds)
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((dsb, CHI_B, CHI_B))
+    Kc = rng.standard_normal((dm_out, CHI_B, DG))
+    X = rng.standard_normal((ds, DG, S))                  # rows sigma = a + da b
+    A_o, K_o = A.transpose(1, 0, 2), Kc.transpose(1, 0, 2)
+    X_o = X.reshape(db, da, DG, S).transpose(1, 0, 2, 3)
+    DX = pk.diagram_apply(cl, R_ROW, K_MED, 0, _dev(torch, A), _dev(torch, Kc), _dev(torch, X)).cpu().numpy()
+    # rho samples: the ends, both sides of a 256 boundary, the middle (the
+    # oracle's sampled form costs seconds per rho)
+    rhos = _sample(dm_in, (0, -1, 255, 256, dm_in // 2))
+    ref = ops.med_apply(c, A_o, K_o, X_o, rhos=rhos)   # (Da, rho, s)
+    _close(DX[rhos], ref.transpose(1, 0, 2), "mediating apply")
+    # transpose by the adjoint identity <Y, D X> = <D^T Y, X>
+    Y = rng.standard_normal((dm_in, CHI_B, S))
+    DtY = pk.diagram_apply(cl, R_ROW, K_MED, 1, _dev(torch, A), _dev(torch, Kc), _dev(torch, Y)).cpu().numpy()
+    for j in (0, 17, S - 1):
+        lhs = float(np.sum(Y[:, :, j] * DX[:, :, j]))
+        rhs = float(np.sum(DtY[:, :, j] * X[:, :, j]))
+        scale = np.sqrt(np.sum(Y[:, :, j] ** 2) * np.sum(DX[:, :, j] ** 2))
+        assert abs(lhs - rhs) <= 1e-12 * scale, (j, lhs, rhs)
+    # left transfer: L [rho][a][t], phi [sigma][t][g]
+    L = rng.standard_normal((dm_in, CHI_B, DG))
+    phi = rng.standard_normal((ds, DG, DG))
+    got = pk.diagram_apply(cl, R_ROW, K_MED, 2, _dev(torch, A), _dev(torch, L), _dev(torch, phi)).cpu().numpy()
+    ells = _sample(dm_out, (0, -1))
+    ref = ops.med_left(c, A_o, L.transpose(1, 0, 2), phi.transpose(1, 0, 2), ells=ells)   # (Db, l, g)
+    _close(got[ells], ref.transpose(1, 0, 2), "mediating left transfer")
+
+
+@pytest.mark.parametrize("r,k", [(1, 1), (2, 1), (2, 3), (1, 5)])
+def test_small_mediating_transpose_and_left_match_oracle(setup, r, k):
+    # the mediating diagrams at the row ends (legs of 4096) against the
+    # oracle in full, all three forms
+    pk, torch, inst, net, cl = setup
+    c = (k - 1) // 2
+    ops = RowOps(net, r)
+    dm_in, dm_out, ds, dsb = pk.diagram_dims(cl, r, k)
+    if dm_in * dm_out > 4096 * 4096:
+        pytest.skip("full oracle too slow for this diagram")
+    da, db = net.phys_dims(r)[1][k]
+    rng = np.random.default_rng(13 + 10 * r + k)
+    A = rng.standard_normal((dsb, CHI_B, CHI_B))
+    Kc = rng.standard_normal((dm_out, CHI_B, DG))
+    X = rng.standard_normal((ds, DG, S))
+    Y = rng.standard_normal((dm_in, CHI_B, S))
+    A_o, K_o = A.transpose(1, 0, 2), Kc.transpose(1, 0, 2)
+    got = pk.diagram_apply(cl, r, k, 0, _dev(torch, A), _dev(torch, Kc), _dev(torch, X)).cpu().numpy()
+    ref = ops.med_apply(c, A_o, K_o, X.reshape(db, da, DG, S).transpose(1, 0, 2, 3))
+    _close(got, ref.transpose(1, 0, 2), "apply")
+    got = pk.diagram_apply(cl, r, k, 1, _dev(torch, A), _dev(torch, Kc), _dev(torch, Y)).cpu().numpy()
+    ref = ops.med_applyT(c, A_o, K_o, Y.transpose(1, 0, 2))                  # (da, db, Dg, s)
+    _close(got, ref.transpose(1, 0, 2, 3).reshape(ds, DG, S), "transpose")
+    L = rng.standard_normal((dm_in, CHI_B, DG))
+    phi = rng.standard_normal((ds, DG, DG))
+    got = pk.diagram_apply(cl, r, k, 2, _dev(torch, A), _dev(torch, L), _dev(torch, phi)).cpu().numpy()
+    ref = ops.med_left(c, A_o, L.transpose(1, 0, 2), phi.transpose(1, 0, 2))
+    _close(got, ref.transpose(1, 0, 2), "left transfer")
+
+
+def test_diagram_apply_rejects_bad_arguments(setup):
+    pk, torch, inst, net, cl = setup
+    A = torch.zeros((256, 16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(pk.TnbError) as e:
+        pk.diagram_dims(cl, 7, 0)
+    assert e.value.code == -1
+    with pytest.raises(pk.TnbError) as e:
+        pk.diagram_apply(cl, R_ROW, K_SITE, 3, A, A, A)
+    assert e.value.code == -1

@@ -53,10 +53,10 @@ def test_truncated_logz_matches_oracle(kind, kw, chi):
             assert env.site_shape(r, k) == site.shape
 
 
-@pytest.mark.parametrize("chi", [16, 64])
+@pytest.mark.parametrize("chi", [16, 32])
 def test_zephyr_t4_planted_logz_matches_oracle(chi):
     # 16-spin-class cells (t = 4): 256 horizontal bins in 16 register chunks, and at
-    # chi = 64 the sketch is processed in column blocks.  With sparse planted
+    # chi = 32 the sketch (72 columns) is processed in column blocks.  With sparse planted
     # couplings chi = 16 is already exact, so parity is strict.
     pk = _gpu()
     inst, s, E0 = planted_loops(1, 4, 77, loops_per_cell=2)
@@ -66,19 +66,20 @@ def test_zephyr_t4_planted_logz_matches_oracle(chi):
 
 
 def test_zephyr_t4_random_logz_within_conditioning():
-    # Random couplings on Z_1 (t = 4) at chi = 64: the truncated zipper is
-    # ill-conditioned here (a 1e-14 relative change of J moves the oracle's own
-    # log Z by 2-4e-6), so GPU and CPU rounding lead to different truncations.
-    # The bound is ten times the conditioning measured in this test.
+    # Random couplings on Z_1 (t = 4) at chi = 32: a truncated zipper can be
+    # ill-conditioned (a 1e-14 relative change of J moves the oracle's own
+    # log Z), so GPU and CPU rounding may lead to different truncations.  The
+    # bound is ten times the conditioning measured in this test, floored at
+    # the 1e-5 relative target.
     import copy
     pk = _gpu()
     inst = make_instance("zephyr", 202, jdist="uniform", hdist="uniform0.1", m=1, t=4)
-    o = Options(chi=64, power=2, cut=1e-6, seed=777)
+    o = Options(chi=32, power=2, cut=1e-6, seed=777)
     ora = contract_env(inst, 1.0, o).logZ
     pert = copy.deepcopy(inst)
     pert.J = inst.J * (1 + 1e-14 * np.cos(np.arange(len(inst.J))))
     spread = abs(contract_env(pert, 1.0, o).logZ - ora)
-    env = pk.Env(pk.Clusters(inst, 1.0), pk.EnvOptions(chi=64, power_iters=2, cut=1e-6, seed=777))
+    env = pk.Env(pk.Clusters(inst, 1.0), pk.EnvOptions(chi=32, power_iters=2, cut=1e-6, seed=777))
     assert abs(env.logZ - ora) <= max(1e-5 * abs(ora), 10 * spread), (env.logZ, ora, spread)
 
 
