@@ -125,34 +125,44 @@ def test_mediating_diagram_full_size(setup):
     _close(got[ells], ref.transpose(1, 0, 2), "mediating left transfer")
 
 
-@pytest.mark.parametrize("r,k", [(1, 1), (2, 1), (2, 3), (1, 5)])
-def test_small_mediating_transpose_and_left_match_oracle(setup, r, k):
-    # the mediating diagrams at the row ends (legs of 4096) against the
-    # oracle in full, all three forms
-    pk, torch, inst, net, cl = setup
-    c = (k - 1) // 2
+@pytest.fixture(scope="module")
+def small():
+    # Zephyr Z_2 with t = 2 (8-spin cells): every diagram small enough for the
+    # oracle in full (mediating legs up to 256 x 256)
+    pk, torch = _gpu()
+    inst = make_instance("zephyr", 1000, jdist="uniform", hdist="uniform0.1", m=2, t=2)
+    return pk, torch, inst, Network(inst, 1.0), pk.Clusters(inst, 1.0)
+
+
+@pytest.mark.parametrize("r,k", [(1, 1), (1, 2), (1, 3), (1, 5), (2, 1), (2, 3), (2, 4), (2, 5)])
+def test_all_forms_match_oracle_in_full(small, r, k):
+    pk, torch, inst, net, cl = small
     ops = RowOps(net, r)
     dm_in, dm_out, ds, dsb = pk.diagram_dims(cl, r, k)
-    if dm_in * dm_out > 4096 * 4096:
-        pytest.skip("full oracle too slow for this diagram")
-    da, db = net.phys_dims(r)[1][k]
     rng = np.random.default_rng(13 + 10 * r + k)
     A = rng.standard_normal((dsb, CHI_B, CHI_B))
     Kc = rng.standard_normal((dm_out, CHI_B, DG))
     X = rng.standard_normal((ds, DG, S))
     Y = rng.standard_normal((dm_in, CHI_B, S))
-    A_o, K_o = A.transpose(1, 0, 2), Kc.transpose(1, 0, 2)
-    got = pk.diagram_apply(cl, r, k, 0, _dev(torch, A), _dev(torch, Kc), _dev(torch, X)).cpu().numpy()
-    ref = ops.med_apply(c, A_o, K_o, X.reshape(db, da, DG, S).transpose(1, 0, 2, 3))
-    _close(got, ref.transpose(1, 0, 2), "apply")
-    got = pk.diagram_apply(cl, r, k, 1, _dev(torch, A), _dev(torch, Kc), _dev(torch, Y)).cpu().numpy()
-    ref = ops.med_applyT(c, A_o, K_o, Y.transpose(1, 0, 2))                  # (da, db, Dg, s)
-    _close(got, ref.transpose(1, 0, 2, 3).reshape(ds, DG, S), "transpose")
     L = rng.standard_normal((dm_in, CHI_B, DG))
     phi = rng.standard_normal((ds, DG, DG))
-    got = pk.diagram_apply(cl, r, k, 2, _dev(torch, A), _dev(torch, L), _dev(torch, phi)).cpu().numpy()
-    ref = ops.med_left(c, A_o, L.transpose(1, 0, 2), phi.transpose(1, 0, 2))
-    _close(got, ref.transpose(1, 0, 2), "left transfer")
+    A_o, K_o, L_o, phi_o = (a.transpose(1, 0, 2) for a in (A, Kc, L, phi))
+    run = lambda mode, K_, X_: pk.diagram_apply(cl, r, k, mode, _dev(torch, A), _dev(torch, K_),
+                                                _dev(torch, X_)).cpu().numpy()
+    if k % 2 == 0:
+        c = k // 2
+        refs = (ops.site_apply(c, A_o, K_o, X).transpose(1, 0, 2),
+                ops.site_applyT(c, A_o, K_o, Y.transpose(1, 0, 2)),
+                ops.site_left(c, A_o, L_o, phi_o).transpose(1, 0, 2))
+    else:
+        c = (k - 1) // 2
+        da, db = net.phys_dims(r)[1][k]
+        refs = (ops.med_apply(c, A_o, K_o, X.reshape(db, da, DG, S).transpose(1, 0, 2, 3)).transpose(1, 0, 2),
+                ops.med_applyT(c, A_o, K_o, Y.transpose(1, 0, 2)).transpose(1, 0, 2, 3).reshape(ds, DG, S),
+                ops.med_left(c, A_o, L_o, phi_o).transpose(1, 0, 2))
+    _close(run(0, Kc, X), refs[0], "apply")
+    _close(run(1, Kc, Y), refs[1], "transpose")
+    _close(run(2, L, phi), refs[2], "left transfer")
 
 
 def test_diagram_apply_rejects_bad_arguments(setup):
