@@ -69,6 +69,19 @@ typedef struct tnb_beam tnb_beam;
 tnb_status tnb_energies(const tnb_instance* inst, const int8_t* d_states, int64_t K,
                         double* d_E, tnb_stream stream);
 
+/* tnb_energies for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernel and result, bit for bit, with the instance's couplings, fields
+ * and edge lists staged in a static device array of the library (2 MiB per
+ * GPU, held until the process ends) instead of allocated buffers.  The
+ * instance must fit it: 16 * n_edges + 8 * n_spins <= 2 MiB, else
+ * TNB_EUNSUPPORTED before any copy.  Every call on one GPU shares that
+ * array, so calls that overlap on a GPU (other threads, other streams) race;
+ * the call synchronises `stream` before it returns.  Other errors as
+ * tnb_energies. */
+tnb_status tnb_energies_noalloc(const tnb_instance* inst, const int8_t* d_states, int64_t K,
+                                double* d_E, tnb_stream stream);
+
 /* Clustered Hamiltonian, Eq. (3)-(5), and Boltzmann weights, Eq. (6).
  * Builds, on the device, for every cluster n the local energies
  * E_n[x], x in [0, 2^k_n) (intra-cluster couplings in edge order, then the

@@ -24,6 +24,7 @@ class TnbEnvOpts(ctypes.Structure):
 # name -> (restype, argtypes)
 SIGNATURES = {
     "tnb_energies": (c_int32, [P(TnbInstance), c_void_p, c_int64, c_void_p, c_void_p]),
+    "tnb_energies_noalloc": (c_int32, [P(TnbInstance), c_void_p, c_int64, c_void_p, c_void_p]),
     "tnb_build_clusters": (c_int32, [P(TnbInstance), c_double, c_void_p, P(c_void_p)]),
     "tnb_cluster_energies": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
     "tnb_bond_energies": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_int64, P(c_int32),

@@ -3,6 +3,7 @@
 // stores; these kernels are bound by the HBM write of the tables.
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <numeric>
 
 #include "model.h"
@@ -192,6 +193,63 @@ extern "C" tnb_status tnb_energies(const tnb_instance* inst, const int8_t* d_sta
                        K, L.N, L.E, ei.p, ej.p, J.p, h.p, d_E);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(s));  // temporaries are freed on return
+  });
+}
+
+// ---- Eq. (1) without device allocation -----------------------------------
+// Staging area for the instance (J, h, edge lists) of tnb_energies_noalloc:
+// a file-scope device array, one copy per GPU, held for the life of the
+// process.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+namespace tnb {
+namespace {
+constexpr size_t kStageBytes = size_t(2) << 20;  // 2 MiB
+__device__ __align__(256) double scratch[kStageBytes / sizeof(double)];
+
+std::mutex g_stage_mu;
+char* g_stage[64] = {nullptr};
+
+char* stage_area() {
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(TNB_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_stage_mu);
+  if (!g_stage[dev]) {
+    void* p = nullptr;
+    HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_stage[dev] = static_cast<char*>(p);
+  }
+  return g_stage[dev];
+}
+}  // namespace
+}  // namespace tnb
+
+extern "C" tnb_status tnb_energies_noalloc(const tnb_instance* inst, const int8_t* d_states, int64_t K,
+                                           double* d_E, tnb_stream stream) {
+  return guarded([&] {
+    Lattice L = validate_instance(inst);
+    if (K < 0) fail(TNB_EINVAL, "K < 0");
+    const size_t bytes = 16 * size_t(L.E) + 8 * size_t(L.N);
+    if (bytes > kStageBytes)
+      fail(TNB_EUNSUPPORTED, "instance exceeds the 2 MiB staging area (16 bytes per edge + 8 per spin)");
+    if (K == 0) return;
+    if (!d_states || !d_E) fail(TNB_EINVAL, "device pointer is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = stage_area();
+    double* J = reinterpret_cast<double*>(base);
+    double* h = J + L.E;
+    int* ei = reinterpret_cast<int*>(h + L.N);
+    int* ej = ei + L.E;
+    if (L.E) {
+      HIPC(hipMemcpyAsync(J, L.J.data(), size_t(L.E) * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPC(hipMemcpyAsync(ei, L.ei.data(), size_t(L.E) * sizeof(int), hipMemcpyHostToDevice, s));
+      HIPC(hipMemcpyAsync(ej, L.ej.data(), size_t(L.E) * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    if (L.N) HIPC(hipMemcpyAsync(h, L.h.data(), size_t(L.N) * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(ising_energy_kernel, dim3(unsigned(cdiv(K, 128))), dim3(128), 0, s, d_states, K, L.N, L.E,
+                       ei, ej, J, h, d_E);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));  // the host copies of the instance end with this call
   });
 }
 
