@@ -31,19 +31,22 @@ WORKLOADS = {
 }
 
 PEAK = {"alu_fp64_tflops": 78.6, "hbm_gbs": 8000.0}  # FP64 vector and FP64 MFMA peaks are equal
-MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_G2", "medf_out", "renv_V", "adj_v"}
+MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_G2", "medf_out", "medf_lbin", "medf_lacc", "renv_V", "adj_v",
+                "site_apply", "site_applyT", "site_left", "gemm"}
+# library timer -> the kernel instance rocprofv3 reports for it
+ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0>", "medf_W2": "medf_bin_pipe<1, 1, 0>",
+                "medf_lbin": "medf_bin_pipe<0, 1, 1>"}
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
 # Valid only for the kernel source they were taken on (hash of its file).
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "medf_Y2_zephyr_z2_t4_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_16431_amd", "csrc", "env.hip")
 
 
 def measured_traffic(kernel, workload):
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))) as fh:
             rec = json.load(fh)
         with open(KERNEL_SRC, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
@@ -52,6 +55,70 @@ def measured_traffic(kernel, workload):
     if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("source_sha256") != sha:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def kernel_table(prof, steps):
+    """Every timed kernel: time per step, launches, achieved rate and its
+    fraction of the FP64 peak (matrix cores and vector units peak alike on
+    MI355X) and of HBM bandwidth, from the algorithmic flop and byte counts."""
+    out = {}
+    for name, (ms, n, fl, by) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
+        if n == 0 or ms <= 0:
+            continue
+        sec = ms / 1000.0
+        tf, gbs = fl / sec / 1e12, by / sec / 1e9
+        out[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps, "avg_ms": ms / n,
+                     "unit_class": "mfma" if name in MFMA_KERNELS else "alu",
+                     "tflops": tf, "frac_fp64_peak": tf / PEAK["alu_fp64_tflops"],
+                     "gbs": gbs, "frac_hbm": gbs / PEAK["hbm_gbs"]}
+    return out
+
+
+def write_traffic(fetch_csv, write_csv, timer, workload, copy_bytes=8 << 27):
+    """HBM bytes per launch of one kernel from two rocprofv3 --pmc passes
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by the same
+    counter's reading for the plain 1 GiB device copy that ends the run
+    (--copy-calibration); the record goes to profiles/ with the hash of the
+    kernel source it was taken on."""
+    import csv
+    import hashlib
+
+    def read(path, counter):
+        per = {}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                d = int(row["Dispatch_Id"])
+                name, v = row["Kernel_Name"], float(row["Counter_Value"])
+                per.setdefault(d, [name, 0.0])[1] += v
+        return per
+
+    kname = ROCPROF_NAME[timer]
+    out = {"kernel": timer, "rocprof_kernel": kname, "workload": workload}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = read(path, counter)
+        copies = [v for d, (n, v) in sorted(per.items()) if "copy" in n.lower()]
+        mine = [v for n, v in per.values() if kname in n]
+        if not copies or not mine:
+            raise SystemExit("no %s dispatches of %s or of the copy in %s" % (counter, kname, path))
+        factor = copies[-1] * 1024.0 / copy_bytes
+        key = "fetch" if counter == "FETCH_SIZE" else "write"
+        out[key + "_bytes_per_launch"] = sum(mine) / len(mine) * 1024.0 / factor
+        out[key + "_factor"] = factor
+        out["launches"] = len(mine)
+    out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    with open(KERNEL_SRC, "rb") as fh:
+        out["source_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+    out["commands"] = [
+        "rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_%s -o %s -- python3 bench.py --steps 1 "
+        "--warmup 0 --no-cpu-baseline --no-planted --copy-calibration" % (c, c.split("_")[0].lower(),
+                                                                          c.split("_")[0].lower())
+        for c in ("FETCH_SIZE", "WRITE_SIZE")]
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (timer, workload))
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def parse():
@@ -66,6 +133,9 @@ def parse():
                     help="skip the planted-instance energy gap (profiling runs: keeps rocprof's kernel averages to the timed workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 1 GiB device copy, the reference dispatch for HBM byte counters")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no run: turn two rocprofv3 counter files of the dominant kernel into profiles/*_traffic.json")
+    ap.add_argument("--traffic-kernel", default="medf_Y2")
     return ap.parse_args()
 
 
@@ -174,6 +244,9 @@ def planted_gap(pk, wl, env_kw):
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic[0], args.write_traffic[1], args.traffic_kernel, args.workload)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (there is no multi-GPU path); got --gpus %d"
               % args.gpus, file=sys.stderr)
@@ -244,6 +317,7 @@ def main():
         "logZ": res["logZ"], "spin_marginals_per_step": marg,
         "roofline": roof, "cpu_baseline": cpu, "adjoint": adj,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
+        "kernels": kernel_table(prof, args.steps),
     }
     print(json.dumps(out), flush=True)
     if args.copy_calibration:

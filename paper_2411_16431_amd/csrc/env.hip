@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
 // The register budget is capped at four waves per SIMD (128 registers, a few
 // spilled outside the item loop): the extra wave hides more load latency than
 // the spills cost.
-template <int MODE, int NJ>
+template <int MODE, int NJ, int VIEW = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const double* __restrict__ P,
                                                      const double* __restrict__ Q, int Da, int Db, int Kd, int s,
                                                      double* __restrict__ out) {
@@ -571,7 +571,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
 // (Db <= 32).  P is read as [item][k][row] (16 consecutive rows per load):
 // MODE 0 gets the connector as stored ([l][b][g]), MODE 1 a transposed copy
 // of the MPS site ([sigma][b][a]).
-template <int MODE, int NJ>
+template <int MODE, int NJ, int VIEW = 0>
 __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __restrict__ P,
                                                      const double* __restrict__ Q, int rows, int Db, int Dr2, int s,
                                                      double* __restrict__ out) {
@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
 // One wave per output block for apply (its x range is short); four waves
 // splitting the x range of an output block for applyT, summed through LDS.
 // apply is capped at five waves per SIMD; NJ <= 3 fits that without spilling.
-template <int NJ>
+template <int NJ, int VIEW = 0>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
                                                       uint32_t Bup, uint32_t Bdn, const double* __restrict__ w,
                                                       const double* __restrict__ A, int Da, int Db,
@@ -1317,8 +1317,21 @@ struct Zipper {
                        double(c.dR) * Db * s + double(c.dR) * nfree));
       // the site chain with P^L and P^R exchanged: A^T (Db x Da), L[l] (Da x t), Pt[u] (t x s)
       if (Db <= 16 && Da <= 16 && t <= 32 && s <= 64) {
-        TNB_SITE_LAUNCH((s + 15) / 16, site_apply_mfma, dim3(c.dR), dim3(64), st, c.PR, FREE, nfree, c.PL, c.Bup,
-                        c.Bdn, c.w, AT.p, Db, Da, Lin, t, Q, s, out);
+        // VIEW = 1: the same code as the apply, a separate instance so that
+        // profiles tell the two uses apart
+        switch ((s + 15) / 16) {
+#define TNB_LEFT_SITE(NJV)                                                                                       \
+  case NJV:                                                                                                      \
+    hipLaunchKernelGGL((site_apply_mfma<NJV, 1>), dim3(c.dR), dim3(64), 0, st, c.PR, FREE, nfree, c.PL, c.Bup,    \
+                       c.Bdn, c.w, AT.p, Db, Da, Lin, t, Q, s, out);                                             \
+    break;
+          TNB_LEFT_SITE(1)
+          TNB_LEFT_SITE(2)
+          TNB_LEFT_SITE(3)
+          TNB_LEFT_SITE(4)
+#undef TNB_LEFT_SITE
+          default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+        }
       } else {
         allow_big_lds(site_apply_kernel, size_t(Da) * s * sizeof(double));
         hipLaunchKernelGGL(site_apply_kernel, dim3(c.dR), dim3(256), size_t(Da) * s * sizeof(double), st, k, c.PR,
@@ -1337,8 +1350,8 @@ struct Zipper {
                           double(mm.drd) * mm.db2 * f.nHR * Da * s));
         if (t <= 32) {
           const unsigned G = unsigned(mm.drd * mm.db2 * f.chR);
-          hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3((G + 7) / 8 * 8 * nj, (Da + 15) / 16), dim3(256), 0, st, f,
-                             LT.p, Q, Db, Da, t, s, Yf.p);
+          hipLaunchKernelGGL((medf_bin_pipe<0, 1, 1>), dim3((G + 7) / 8 * 8 * nj, (Da + 15) / 16), dim3(256), 0, st,
+                             f, LT.p, Q, Db, Da, t, s, Yf.p);
         } else {
           const size_t shm = medf_bin_lds(t, nj);
           check_lds(shm);
@@ -1352,7 +1365,19 @@ struct Zipper {
                    8.0 * (double(mm.da2) * mm.db2 * Da * Db + double(mm.drd) * mm.db2 * f.nHR * Da * s +
                           double(mm.dR) * Db * s));
         if (Da <= 32) {
-          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(mm.dR, (Db + 15) / 16), 0, st, f, AT.p, Yf.p, Db, Da, 0, s, out);
+          switch (nj) {
+#define TNB_LEFT_ACC(NJV)                                                                                        \
+  case NJV:                                                                                                      \
+    hipLaunchKernelGGL((medf_acc_pipe<1, NJV, 1>), dim3(mm.dR, (Db + 15) / 16), dim3(256), 0, st, f, AT.p, Yf.p,  \
+                       Db, Da, 0, s, out);                                                                       \
+    break;
+            TNB_LEFT_ACC(1)
+            TNB_LEFT_ACC(2)
+            TNB_LEFT_ACC(3)
+            TNB_LEFT_ACC(4)
+#undef TNB_LEFT_ACC
+            default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+          }
         } else {
           TNB_NJ_LAUNCH(nj, medf_acc_mfma, 1, dim3(mm.dR, (Db + 15) / 16), 0, st, f, AT2.p, Yf.p, Db, Da, 0, s,
                         out);
