@@ -30,9 +30,19 @@ WORKLOADS = {
                                hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
 }
 
-PEAK = {"alu_fp64_tflops": 78.6, "hbm_gbs": 8000.0}  # FP64 vector and FP64 MFMA peaks are equal
+# MI355X: FP64 vector and FP64 MFMA peaks are equal; FP32 MFMA (dense) and FP32 vector are 157.3
+PEAK = {"alu_fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_G2", "medf_out", "medf_lbin", "medf_lacc", "renv_V", "adj_v",
                 "site_apply", "site_applyT", "site_left", "gemm"}
+
+
+def peak_of(name):
+    """Peak of a timed kernel: FP32 for the *_f32 diagram kernels, else FP64."""
+    return PEAK["fp32_tflops"] if name.endswith("_f32") else PEAK["alu_fp64_tflops"]
+
+
+def unit_class(name):
+    return "mfma" if name.replace("_f32", "") in MFMA_KERNELS else "alu"
 # library timer -> the kernel instance rocprofv3 reports for it
 ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0>", "medf_W2": "medf_bin_pipe<1, 1, 0>",
                 "medf_lbin": "medf_bin_pipe<0, 1, 1>"}
@@ -68,9 +78,8 @@ def kernel_table(prof, steps):
         sec = ms / 1000.0
         tf, gbs = fl / sec / 1e12, by / sec / 1e9
         out[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps, "avg_ms": ms / n,
-                     "unit_class": "mfma" if name in MFMA_KERNELS else "alu",
-                     "tflops": tf, "frac_fp64_peak": tf / PEAK["alu_fp64_tflops"],
-                     "gbs": gbs, "frac_hbm": gbs / PEAK["hbm_gbs"]}
+                     "unit_class": unit_class(name), "tflops": tf, "peak_tflops": peak_of(name),
+                     "frac_peak": tf / peak_of(name), "gbs": gbs, "frac_hbm": gbs / PEAK["hbm_gbs"]}
     return out
 
 
@@ -128,6 +137,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="zephyr_z2_t4_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32-contraction comparison")
     ap.add_argument("--power-iters", type=int, default=2)
     ap.add_argument("--no-planted", action="store_true",
                     help="skip the planted-instance energy gap (profiling runs: keeps rocprof's kernel averages to the timed workload)")
@@ -226,6 +236,29 @@ def adjoint_compare(pk, torch, env, wl, inst):
             "max_abs_diff_adjoint_vs_per_branch": float((m1 - pb).abs().max().item())}
 
 
+def fp32_compare(pk, torch, inst, wl, env_kw, res64, steps):
+    """The same solve with FP32 diagram contractions: time per step and the
+    error of each result against the FP64 path (log Z, returned energies and
+    states)."""
+    kw = dict(env_kw, prec="f32")
+    pk.solve(inst, wl["beta"], chi=wl["chi"], M=wl["M"], K=wl["K"], **kw)  # warm-up
+    torch.cuda.synchronize()
+    pk.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = pk.solve(inst, wl["beta"], chi=wl["chi"], M=wl["M"], K=wl["K"], **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pk.profile_enable(False)
+    prof = {name: pk.profile_query(name) for name in pk.profile_names()}
+    import numpy as np
+    same = (res["states"].shape == res64["states"].shape and np.array_equal(res["states"], res64["states"]))
+    return {"ms_per_step": dt * 1e3, "value": res["spin_marginals"] / dt, "logZ": res["logZ"],
+            "logZ_rel_err_vs_f64": abs(res["logZ"] - res64["logZ"]) / abs(res64["logZ"]),
+            "best_energy": float(res["energies"][0]), "best_energy_f64": float(res64["energies"][0]),
+            "returned_states_equal_f64": bool(same), "kernels": kernel_table(prof, steps)}
+
+
 def planted_gap(pk, wl, env_kw):
     """Energy gap d_E = (E - E0) / (2 |E0|) (Eq. 14) on a planted instance of
     the same lattice, chi and beam, whose exact ground energy E0 is the sum of
@@ -288,9 +321,9 @@ def main():
     if dom:
         ms, n, fl, by = prof[dom]
         avg_s = ms / 1000.0 / n
-        roof = {"bound": "mfma" if dom in MFMA_KERNELS else "alu", "kernel": dom, "achieved": fl / n / avg_s / 1e12,
-                "peak": PEAK["alu_fp64_tflops"], "unit": "TFLOP/s",
-                "frac": fl / n / avg_s / 1e12 / PEAK["alu_fp64_tflops"],
+        roof = {"bound": unit_class(dom), "kernel": dom, "achieved": fl / n / avg_s / 1e12,
+                "peak": peak_of(dom), "unit": "TFLOP/s",
+                "frac": fl / n / avg_s / 1e12 / peak_of(dom),
                 "traffic": measured_traffic(dom, args.workload), "traffic_unit": "bytes per launch",
                 "algorithmic_bytes_per_launch": by / n,
                 "avg_ms": ms / n, "launches_per_step": n / args.steps,
@@ -299,6 +332,8 @@ def main():
               "med": (prof.get("med_apply", (0, 0))[1] + prof.get("med_applyT", (0, 0))[1]
                       + prof.get("medf_Y2", (0, 0))[1] + prof.get("medf_W2", (0, 0))[1]) / args.steps}
     adj = adjoint_compare(pk, torch, res["env"], wl, inst)
+    f32 = None if args.no_f32 else fp32_compare(pk, torch, inst, wl, env_kw, res, args.steps)
+    print("fp32 comparison done", file=sys.stderr, flush=True)
     planted = None if args.no_planted else planted_gap(pk, wl, env_kw)
     print("adjoint comparison done", file=sys.stderr, flush=True)
     cpu = None
@@ -315,7 +350,7 @@ def main():
                    "power_iters": args.power_iters},
         "best_energy": float(res["energies"][0]), "energy_gap_vs_oracle": None, "energy_gap_planted": planted,
         "logZ": res["logZ"], "spin_marginals_per_step": marg,
-        "roofline": roof, "cpu_baseline": cpu, "adjoint": adj,
+        "roofline": roof, "cpu_baseline": cpu, "adjoint": adj, "fp32": f32,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
         "kernels": kernel_table(prof, args.steps),
     }

@@ -40,6 +40,14 @@ typedef enum {
 
 typedef void* tnb_stream;  /* a hipStream_t; NULL is the null stream */
 
+/* Arithmetic of the environment contractions (the benchmark spec's FP32 option,
+ * Sec. VI compares the two).  TNB_F32: the site and mediating diagrams read
+ * FP32 copies of their operands and of the Boltzmann weights (each table
+ * already shifted by its minimum energy, so every weight lies in [0, 1]) and
+ * accumulate in FP32 on the matrix cores; the bond-weight folds, the QR/SVD,
+ * the truncation, the log-scales, the beam and every result stay FP64. */
+typedef enum { TNB_F64 = 0, TNB_F32 = 1 } tnb_prec;
+
 /* One Ising instance, H(s) = sum_e J_e s_i s_j + sum_i h_i s_i (Eq. 1), all
  * arrays in host memory.  Edges e have 0 <= edge_i[e] < edge_j[e] < n_spins,
  * sorted by (i, j), no duplicates.  Every edge must join clusters that are
@@ -120,6 +128,7 @@ typedef struct {
                             (Fig. 8d); 0: none                               */
   int32_t var_sweeps;    /* full one-site variational sweeps of the 2*chi MPS
                             before the chi truncation, 0 .. 8                */
+  int32_t prec;          /* tnb_prec of the diagram contractions             */
 } tnb_env_opts;
 
 /* Boundary MPSs Psi_R .. Psi_1 of the lower half-lattice (Fig. 6, 8) and
@@ -159,10 +168,12 @@ tnb_status tnb_diagram_dims(const tnb_clusters* cl, int32_t r, int32_t k, int32_
  *                right, Fig. 8d): d_K the left environment [dm_in][Da][Dg];
  *                d_X the new site [ds][Dg][s]; d_out [dm_out][Db][s].
  * 1 <= Da, Db, Dg <= 128, 1 <= s <= 256; out_len is d_out's capacity in
- * doubles.  The product path of tnb_contract_env runs the same kernels.
+ * doubles.  prec (tnb_prec) selects the arithmetic of the diagram kernels;
+ * the tensors are FP64 either way.  The product path of tnb_contract_env
+ * runs the same kernels.
  * Errors: TNB_EINVAL (handle, indices, sizes, NULL tensors),
  * TNB_EUNSUPPORTED (tiles beyond the LDS), TNB_ENOMEM. */
-tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32_t mode,
+tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32_t mode, int32_t prec,
                              const double* d_A, int32_t Da, int32_t Db, const double* d_K,
                              int32_t Dg, const double* d_X, int32_t s, double* d_out,
                              int64_t out_len, tnb_stream stream);

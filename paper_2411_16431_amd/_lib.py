@@ -18,7 +18,7 @@ class TnbInstance(ctypes.Structure):
 class TnbEnvOpts(ctypes.Structure):
     _fields_ = [("chi", c_int32), ("sketch_extra", c_int32), ("power_iters", c_int32),
                 ("cut", c_double), ("seed", ctypes.c_uint64), ("var_window", c_int32),
-                ("var_sweeps", c_int32)]
+                ("var_sweeps", c_int32), ("prec", c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -33,7 +33,7 @@ SIGNATURES = {
     "tnb_env_site_shape": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int32), P(c_int32)]),
     "tnb_diagram_dims": (c_int32, [c_void_p, c_int32, c_int32, P(c_int32), P(c_int32), P(c_int32),
                                    P(c_int32)]),
-    "tnb_diagram_apply": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32,
+    "tnb_diagram_apply": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32,
                                     c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
     "tnb_beam_create": (c_int32, [c_void_p, c_int32, P(c_void_p)]),
     "tnb_beam_info": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),

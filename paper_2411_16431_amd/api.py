@@ -112,6 +112,9 @@ class Clusters(_Handle):
         return out.reshape(r.value, c.value)
 
 
+PRECS = {"f64": 0, "f32": 1}
+
+
 @dataclass
 class EnvOptions:
     chi: int = 16
@@ -121,10 +124,11 @@ class EnvOptions:
     seed: int = 12345
     var_window: int = 2
     var_sweeps: int = 1
+    prec: str = "f64"      # "f64" or "f32": arithmetic of the diagram contractions
 
     def c(self):
         return L.TnbEnvOpts(self.chi, self.sketch_extra, self.power_iters, self.cut, self.seed,
-                            self.var_window, self.var_sweeps)
+                            self.var_window, self.var_sweeps, PRECS[self.prec])
 
 
 class Env(_Handle):
@@ -232,7 +236,7 @@ def diagram_dims(clusters, r, k):
     return a.value, b.value, c.value, d.value
 
 
-def diagram_apply(clusters, r, k, mode, A, K, X):
+def diagram_apply(clusters, r, k, mode, A, K, X, prec="f64"):
     """tnb_diagram_apply on float64 cuda tensors: A [ds_below][Da][Db],
     K [dm_out][Db][Dg] (modes 0, 1) or [dm_in][Da][Dg] (mode 2), X as in the
     header; returns the output tensor."""
@@ -252,7 +256,7 @@ def diagram_apply(clusters, r, k, mode, A, K, X):
     for t in (A, K, X):
         assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
     out = torch.empty(shape, dtype=torch.float64, device=A.device)
-    _check(L.lib().tnb_diagram_apply(clusters._h, int(r), int(k), int(mode), ctypes.c_void_p(A.data_ptr()),
+    _check(L.lib().tnb_diagram_apply(clusters._h, int(r), int(k), int(mode), PRECS[prec], ctypes.c_void_p(A.data_ptr()),
                                      int(Da), int(Db), ctypes.c_void_p(K.data_ptr()), int(Dg),
                                      ctypes.c_void_p(X.data_ptr()), int(s), ctypes.c_void_p(out.data_ptr()),
                                      out.numel(), _stream()))

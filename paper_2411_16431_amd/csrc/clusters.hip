@@ -167,6 +167,26 @@ const double* unit_weight() {
   return ptr[dev];
 }
 
+const float* unit_weight32() {
+  static float* ptr[64] = {nullptr};
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(TNB_EDEVICE, "device index out of range");
+  if (!ptr[dev]) {
+    float* p = nullptr;
+    HIPC(hipMalloc(reinterpret_cast<void**>(&p), sizeof(float)));
+    const float one = 1.0f;
+    HIPC(hipMemcpy(p, &one, sizeof(float), hipMemcpyHostToDevice));
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = float(x[i]);
+}
+
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace tnb
@@ -377,6 +397,14 @@ extern "C" tnb_status tnb_build_clusters(const tnb_instance* inst, double beta, 
                          d_blen.p, d_bmin.p);
       hipLaunchKernelGGL(boltzmann_kernel, dim3(unsigned(cdiv(maxent, 256)), nb), dim3(256), 0, s,
                          cl->E_bond.p, cl->W_bond.p, d_boff.p, d_blen.p, d_bmin.p, beta);
+    }
+    // FP32 copies of every weight table (exp(-beta (E - E_min)) lies in [0, 1])
+    {
+      const int64_t nl = cl->loc_off[ncell], nbw = int64_t(cl->W_bond.n);
+      cl->w_loc32.alloc(size_t(std::max<int64_t>(nl, 1)));
+      cl->W_bond32.alloc(size_t(std::max<int64_t>(nbw, 1)));
+      if (nl) hipLaunchKernelGGL(to_f32_kernel, dim3(unsigned(cdiv(nl, 256))), dim3(256), 0, s, cl->w_loc.p, nl, cl->w_loc32.p);
+      if (nb) hipLaunchKernelGGL(to_f32_kernel, dim3(unsigned(cdiv(nbw, 256))), dim3(256), 0, s, cl->W_bond.p, nbw, cl->W_bond32.p);
     }
     HIPC(hipGetLastError());
     cl->E_min_loc.resize(ncell);

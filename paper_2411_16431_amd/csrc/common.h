@@ -122,6 +122,7 @@ Lattice validate_instance(const tnb_instance* inst);
 // A device double holding 1.0 for the current device (allocated once per
 // device and kept for the life of the process).
 const double* unit_weight();
+const float* unit_weight32();
 
 template <class F>
 tnb_status guarded(F&& f) {

@@ -26,6 +26,7 @@ struct RowGeom {
     uint32_t PL = 0, PR = 0, Bup = 0, Bdn = 0;
     int dL = 1, dR = 1, du = 1, dv = 1, dvd = 1;  // dv: Psi_r site 2c; dvd: Psi_{r+1} site 2c
     const double* w = nullptr;
+    const float* w32 = nullptr;  // the same weights in FP32
     const double* Wv = nullptr;  // W(v, u) = Wv[v*Wv_sp + u*Wv_sq]
     int64_t Wv_sp = 0, Wv_sq = 0;
   };
@@ -36,6 +37,7 @@ struct RowGeom {
     uint32_t pos_d_rho = 0, pos_d_ell = 0;   // ... of the bits facing the upper diagonal cells
     uint32_t pos_a2 = 0, pos_b2 = 0;         // ... of the bits facing the lower diagonal cells
     const double* Wh = nullptr;
+    const float* Wh32 = nullptr;             // the same table in FP32
     int64_t Wh_sp = 0, Wh_sq = 0;
     const double* Wdr = nullptr;             // W(a, l_d)
     int64_t Wdr_sp = 0, Wdr_sq = 0;

@@ -61,6 +61,7 @@ RowGeom row_geom(const tnb_clusters* cl, int r) {
     col.dv = 1 << popcount32(cl->B(col.up, n));
     col.dvd = 1 << popcount32(col.Bdn);
     col.w = cl->w_loc.p + cl->loc_off[n];
+    col.w32 = cl->w_loc32.p + cl->loc_off[n];
     view(col.up, n, &col.Wv, &col.Wv_sp, &col.Wv_sq);
     g.col.push_back(col);
   }
@@ -86,6 +87,8 @@ RowGeom row_geom(const tnb_clusters* cl, int r) {
     md.drd = 1 << popcount32(md.pos_d_rho);
     md.dld = 1 << popcount32(md.pos_d_ell);
     view(n0, n1, &md.Wh, &md.Wh_sp, &md.Wh_sq);
+    md.Wh32 = cl->weight32(n0, n1);
+    if (!md.Wh32) md.Wh32 = unit_weight32();
     view(up0, n1, &md.Wdr, &md.Wdr_sp, &md.Wdr_sq);
     view(up1, n0, &md.Wdl, &md.Wdl_sp, &md.Wdl_sq);
     g.med.push_back(md);
@@ -114,66 +117,70 @@ __global__ void identity_kernel(double* __restrict__ O, int64_t n) {
 }
 
 // out[l] (Da x s) for l = blockIdx.x.  T = K[rho] Xt[u] is staged in LDS.
+template <class T = double>
 __global__ void site_apply_kernel(int k, uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
-                                  uint32_t Bup, uint32_t Bdn, const double* __restrict__ w,
-                                  const double* __restrict__ A, int Da, int Db,
-                                  const double* __restrict__ Kc, int Dg,
-                                  const double* __restrict__ Xt, int s, double* __restrict__ out) {
-  extern __shared__ double T[];  // Db x s
+                                  uint32_t Bup, uint32_t Bdn, const T* __restrict__ w,
+                                  const T* __restrict__ A, int Da, int Db,
+                                  const T* __restrict__ Kc, int Dg,
+                                  const T* __restrict__ Xt, int s, T* __restrict__ out) {
+  extern __shared__ double sh_raw[];
+  T* Tl = reinterpret_cast<T*>(sh_raw);  // Db x s
   const uint32_t l = blockIdx.x;
-  double* o = out + size_t(l) * Da * s;
+  T* o = out + size_t(l) * Da * s;
   for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) o[idx] = 0.0;
   for (int f = 0; f < nfree; ++f) {
     const uint32_t x = pdep_dev(l, PL) | pdep_dev(uint32_t(f), FREE);
-    const double wx = w[x];
-    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;
-    const double* Xu = Xt + size_t(pext_dev(x, Bup)) * Dg * s;
-    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;
+    const T wx = w[x];
+    const T* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;
+    const T* Xu = Xt + size_t(pext_dev(x, Bup)) * Dg * s;
+    const T* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;
     __syncthreads();
     for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
       const int b = idx / s, j = idx % s;
-      double acc = 0.0;
+      T acc = 0;
       for (int g = 0; g < Dg; ++g) acc = fma(Kr[b * Dg + g], Xu[g * s + j], acc);
-      T[idx] = acc;
+      Tl[idx] = acc;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < Da * s; idx += blockDim.x) {
       const int a = idx / s, j = idx % s;
-      double acc = 0.0;
-      for (int b = 0; b < Db; ++b) acc = fma(Av[a * Db + b], T[b * s + j], acc);
+      T acc = 0;
+      for (int b = 0; b < Db; ++b) acc = fma(Av[a * Db + b], Tl[b * s + j], acc);
       o[idx] = fma(wx, acc, o[idx]);
     }
   }
 }
 
 // G[u] (Dg x s) for u = blockIdx.x.
+template <class T = double>
 __global__ void site_applyT_kernel(int k, uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL,
-                                   uint32_t PR, uint32_t Bdn, const double* __restrict__ w,
-                                   const double* __restrict__ A, int Da, int Db,
-                                   const double* __restrict__ Kc, int Dg,
-                                   const double* __restrict__ Y, int s, double* __restrict__ G) {
-  extern __shared__ double T[];  // Db x s
+                                   uint32_t PR, uint32_t Bdn, const T* __restrict__ w,
+                                   const T* __restrict__ A, int Da, int Db,
+                                   const T* __restrict__ Kc, int Dg,
+                                   const T* __restrict__ Y, int s, T* __restrict__ G) {
+  extern __shared__ double sh_raw[];
+  T* Tl = reinterpret_cast<T*>(sh_raw);  // Db x s
   const uint32_t u = blockIdx.x;
-  double* o = G + size_t(u) * Dg * s;
+  T* o = G + size_t(u) * Dg * s;
   for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) o[idx] = 0.0;
   for (int f = 0; f < nfree; ++f) {
     const uint32_t x = pdep_dev(u, Bup) | pdep_dev(uint32_t(f), FREE);
-    const double wx = w[x];
-    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;
-    const double* Yl = Y + size_t(pext_dev(x, PL)) * Da * s;
-    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;
+    const T wx = w[x];
+    const T* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;
+    const T* Yl = Y + size_t(pext_dev(x, PL)) * Da * s;
+    const T* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;
     __syncthreads();
     for (int idx = threadIdx.x; idx < Db * s; idx += blockDim.x) {
       const int b = idx / s, j = idx % s;
-      double acc = 0.0;
+      T acc = 0;
       for (int a = 0; a < Da; ++a) acc = fma(Av[a * Db + b], Yl[a * s + j], acc);
-      T[idx] = acc;
+      Tl[idx] = acc;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < Dg * s; idx += blockDim.x) {
       const int g = idx / s, j = idx % s;
-      double acc = 0.0;
-      for (int b = 0; b < Db; ++b) acc = fma(Kr[b * Dg + g], T[b * s + j], acc);
+      T acc = 0;
+      for (int b = 0; b < Db; ++b) acc = fma(Kr[b * Dg + g], Tl[b * s + j], acc);
       o[idx] = fma(wx, acc, o[idx]);
     }
   }
@@ -201,13 +208,33 @@ struct MedF {
 };
 
 // ---- the factored mediating diagram on the matrix cores -------------------
-// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// and holds D[4 v + l / 16][l % 16] in item v of the result.
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// 16x16x4 MFMA in either precision.  Lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; item v of the result holds row MF<T>::row(v, l / 16),
+// column l % 16:
+//   v_mfma_f64_16x16x4f64  rows 4 v + l / 16   (the four lane groups interleave)
+//   v_mfma_f32_16x16x4f32  rows 4 (l / 16) + v (each lane group holds four rows)
+// A product whose B operand is the previous result (chained in registers)
+// takes the reduction index of k-step kk as MF<T>::row(kk, l / 16), so item kk
+// of the lane's result is exactly the B element it supplies.
+template <class T> struct MF;
+template <> struct MF<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
+  static __device__ __forceinline__ v4 zero() { return v4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ const double* wh(const RowGeom::Med& m) { return m.Wh; }
+};
+template <> struct MF<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+  static __device__ __forceinline__ v4 zero() { return v4{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ const float* wh(const RowGeom::Med& m) { return m.Wh32; }
+};
 
 // Binned two-stage contraction (medf_Y2 and medf_W2).  For the items t of the
 // block's class:
@@ -220,18 +247,19 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 // Four items per round: each wave stages its item's tiles in LDS and forms T_t;
 // the four T_t go through LDS into the B layout of stage 2, where wave w owns
 // rows b = 4w .. 4w+3 of the block's 16-row b tile.
-template <int MODE, int NJ>
-__global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __restrict__ P,
-                                                     const double* __restrict__ Q, int Da, int Db, int Kd, int s,
-                                                     double* __restrict__ out) {
-  extern __shared__ double sh[];
+template <int MODE, int NJ, class T = double>
+__global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const T* __restrict__ P,
+                                                     const T* __restrict__ Q, int Da, int Db, int Kd, int s,
+                                                     T* __restrict__ out) {
+  extern __shared__ double sh_raw[];
+  T* sh = reinterpret_cast<T*>(sh_raw);
   // P rows are padded to a power of two (lgK) so the staging index splits
   // with a shift; the MFMA loop still stops at Kp
   const int Kp = (Kd + 3) & ~3, lgK = 32 - __clz(Kp - 1), PS = (1 << lgK) + 1, QS = 16 * NJ;
-  double* Ps = sh;                  // [4][16][PS]
-  double* Qs = Ps + 4 * 16 * PS;    // [4][Kp][QS]
-  double* Ts = Qs + 4 * Kp * QS;    // [4][16][QS]
-  double* Ws = Ts + 4 * 16 * QS;    // [4][16]
+  T* Ps = sh;                  // [4][16][PS]
+  T* Qs = Ps + 4 * 16 * PS;    // [4][Kp][QS]
+  T* Ts = Qs + 4 * Kp * QS;    // [4][16][QS]
+  T* Ws = Ts + 4 * 16 * QS;    // [4][16]
   const RowGeom::Med& md = f.md;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -243,33 +271,33 @@ __global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __res
   const int nitems = MODE == 0 ? md.dL / md.db2 : md.dR / md.drd;
   const uint32_t fixed_bits = MODE == 0 ? pdep_dev(b2, md.pos_b2) : pdep_dev(rd, md.pos_d_rho);
   const uint32_t free_bits = MODE == 0 ? (uint32_t(md.dL - 1) & ~md.pos_b2) : (uint32_t(md.dR - 1) & ~md.pos_d_rho);
-  double* Pw = Ps + w * 16 * PS;
-  double* Qw = Qs + w * Kp * QS;
-  double* Tw = Ts + w * 16 * QS;
-  double* Ww = Ws + w * 16;
-  v4d acc[4][NJ];
+  T* Pw = Ps + w * 16 * PS;
+  T* Qw = Qs + w * Kp * QS;
+  T* Tw = Ts + w * 16 * QS;
+  T* Ww = Ws + w * 16;
+  typename MF<T>::v4 acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = MF<T>::zero();
   for (int t0 = 0; t0 < nitems; t0 += 4) {
     const int t = t0 + w;
     __syncthreads();  // the previous round's stage 2 is done with Ts and Ws
-    v4d tt[NJ];
+    typename MF<T>::v4 tt[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) tt[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) tt[j] = MF<T>::zero();
     if (t < nitems) {
       const uint32_t item = fixed_bits | pdep_dev(uint32_t(t), free_bits);
-      const double* Pt;
-      const double* Qt;
-      double wgt = 0.0;
+      const T* Pt;
+      const T* Qt;
+      T wgt = 0;
       if (MODE == 0) {
         const uint32_t l = item;
         Pt = P + size_t(l) * Db * Kd;  // K[l][b][g], Kd = Dg
         Qt = Q + (size_t(pext_dev(l, md.pos_d_ell)) * md.drd + rd) * Kd * s;
         if (li < nbins) {
           const uint32_t rho = pdep_dev(rd, md.pos_d_rho) | pdep_dev(chunk * 16u + li, f.hR_pos);
-          wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+          wgt = MF<T>::wh(md)[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
         }
       } else {
         const uint32_t rho = item;
@@ -277,7 +305,7 @@ __global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __res
         Qt = Q + size_t(rho) * Da * s;
         if (li < nbins) {
           const uint32_t l = pdep_dev(b2, md.pos_b2) | pdep_dev(chunk * 16u + li, f.hL_pos);
-          wgt = md.Wh[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
+          wgt = MF<T>::wh(md)[pext_dev(rho, md.pos_h_rho) * md.Wh_sp + pext_dev(l, md.pos_h_ell) * md.Wh_sq];
         }
       }
       if (lane < 16) Ww[lane] = wgt;
@@ -287,41 +315,41 @@ __global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __res
         if (MODE == 0) { r = i >> lgK; k = i & ((1 << lgK) - 1); }
         else { k = i >> 4; r = i & 15; }
         const int b = b0 + r;
-        double v = 0.0;
+        T v = 0;
         if (b < Db && k < Kd) v = MODE == 0 ? Pt[size_t(b) * Kd + k] : Pt[size_t(k) * Db + b];
         Pw[r * PS + k] = v;
       }
       for (int i = lane; i < Kp * QS; i += 64) {
         const int k = i / QS, j = i % QS;
-        Qw[i] = (k < Kd && j < s) ? Qt[size_t(k) * s + j] : 0.0;
+        Qw[i] = (k < Kd && j < s) ? Qt[size_t(k) * s + j] : T(0);
       }
     } else if (lane < 16) {
-      Ww[lane] = 0.0;
+      Ww[lane] = T(0);
     }
     __syncthreads();  // staged tiles visible
     if (t < nitems) {
 #pragma unroll 2
       for (int kk = 0; kk < Kp; kk += 4) {
-        const double a = Pw[li * PS + kk + lk];
+        const T a = Pw[li * PS + kk + lk];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) tt[j] = mfma16(a, Qw[(kk + lk) * QS + 16 * j + li], tt[j]);
+        for (int j = 0; j < NJ; ++j) tt[j] = MF<T>::mma(a, Qw[(kk + lk) * QS + 16 * j + li], tt[j]);
       }
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Tw[(4 * v + lk) * QS + 16 * j + li] = tt[j][v];
+      for (int v = 0; v < 4; ++v) Tw[(MF<T>::row(v, lk)) * QS + 16 * j + li] = tt[j][v];
     __syncthreads();
     // stage 2: A[h][k] = w_k[h], B[k][(b, j)] = T_k[b][j]
-    const double a2 = Ws[lk * 16 + li];
+    const T a2 = Ws[lk * 16 + li];
 #pragma unroll
     for (int bl = 0; bl < 4; ++bl) {
       const int b = 4 * w + bl;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) acc[bl][j] = mfma16(a2, Ts[lk * 16 * QS + b * QS + 16 * j + li], acc[bl][j]);
+      for (int j = 0; j < NJ; ++j) acc[bl][j] = MF<T>::mma(a2, Ts[lk * 16 * QS + b * QS + 16 * j + li], acc[bl][j]);
     }
   }
-  double* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
+  T* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
 #pragma unroll
   for (int bl = 0; bl < 4; ++bl) {
     const int b = b0 + 4 * w + bl;
@@ -332,7 +360,7 @@ __global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __res
       if (jj >= s) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int h = 4 * v + lk;
+        const int h = MF<T>::row(v, lk);
         if (h < nbins) o[(size_t(h) * Db + b) * s + jj] = acc[bl][j][v];
       }
     }
@@ -348,19 +376,19 @@ __global__ void __launch_bounds__(256) medf_bin_mfma(MedF f, const double* __res
 // Wave w takes the items t = w, w+4, ...; the four partial tiles are summed
 // through LDS at the end.  Operands are read straight from global memory:
 // along the lanes of one MFMA operand the addresses are consecutive.
-template <int MODE, int NJ>
-__global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __restrict__ P,
-                                                     const double* __restrict__ Q, int rows, int Db, int Dr2, int s,
-                                                     double* __restrict__ out) {
-  __shared__ double red[4][16][16 * NJ];
+template <int MODE, int NJ, class T = double>
+__global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const T* __restrict__ P,
+                                                     const T* __restrict__ Q, int rows, int Db, int Dr2, int s,
+                                                     T* __restrict__ out) {
+  __shared__ T red[4][16][16 * NJ];
   const RowGeom::Med& md = f.md;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = blockIdx.y * 16;
   const int row = r0 + li;
-  v4d acc[NJ];
+  typename MF<T>::v4 acc[NJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::zero();
   int nitems;
   uint32_t ld = 0, rd = 0, a2 = 0, hR = 0, fixed_bits = 0, free_bits = 0;
   if (MODE == 0) {
@@ -377,8 +405,8 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
     nitems = md.db2;
   }
   for (int t = w; t < nitems; t += 4) {
-    const double* Pt;
-    const double* Qt;
+    const T* Pt;
+    const T* Qt;
     if (MODE == 0) {
       const uint32_t l = fixed_bits | pdep_dev(uint32_t(t), free_bits);
       Pt = P + size_t(l) * Db * rows;  // K[l][b][g]: element (g, b) at b*rows + g
@@ -389,22 +417,22 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
     }
     for (int kk = 0; kk < Db; kk += 4) {
       const int k = kk + lk;
-      double a = 0.0;
+      T a = 0;
       if (row < rows && k < Db) a = MODE == 0 ? Pt[size_t(k) * rows + row] : Pt[size_t(row) * Db + k];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = 16 * j + li;
-        const double b = (k < Db && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
-        acc[j] = mfma16(a, b, acc[j]);
+        const T b = (k < Db && jj < s) ? Qt[size_t(k) * s + jj] : T(0);
+        acc[j] = MF<T>::mma(a, b, acc[j]);
       }
     }
   }
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w][4 * v + lk][16 * j + li] = acc[j][v];
+    for (int v = 0; v < 4; ++v) red[w][MF<T>::row(v, lk)][16 * j + li] = acc[j][v];
   __syncthreads();
-  double* o = out + size_t(blockIdx.x) * rows * s;
+  T* o = out + size_t(blockIdx.x) * rows * s;
   (void)Dr2;
   for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
     const int r = i / (16 * NJ), jj = i % (16 * NJ);
@@ -422,13 +450,13 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const double* __res
 // The register budget is capped at four waves per SIMD (128 registers, a few
 // spilled outside the item loop): the extra wave hides more load latency than
 // the spills cost.
-template <int MODE, int NJ, int VIEW = 0>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const double* __restrict__ P,
-                                                     const double* __restrict__ Q, int Da, int Db, int Kd, int s,
-                                                     double* __restrict__ out) {
+template <int MODE, int NJ, int VIEW = 0, class T = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const T* __restrict__ P,
+                                                     const T* __restrict__ Q, int Da, int Db, int Kd, int s,
+                                                     T* __restrict__ out) {
   constexpr int KK = 8, QS = 16 * NJ;  // reduction <= 4 * KK
-  __shared__ double Ts[4][16][QS];
-  __shared__ double Ws[4][16];
+  __shared__ T Ts[4][16][QS];
+  __shared__ T Ws[4][16];
   const RowGeom::Med& md = f.md;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -478,7 +506,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
     else
       lane_h = pext_dev(pdep_dev(b2, md.pos_b2) | pdep_dev(chunk * 16u + li, f.hL_pos), md.pos_h_ell);
   }
-  double pa[KK], qb[KK][NJ], wr = 0.0;
+  T pa[KK], qb[KK][NJ], wr = 0;
   auto fetch = [&](int t) {
     if (t >= nitems) return;
     uint32_t item, xp, hp;
@@ -492,64 +520,64 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
       xp = fx | pext_dev(fr, xmask);
       hp = fh | pext_dev(fr, hmask);
     }
-    const double* Pt;
-    const double* Qt;
+    const T* Pt;
+    const T* Qt;
     if (MODE == 0) {  // item = l, xp = l_d(l), hp = h'(l); P = K transposed, [l][g][b]
       Pt = P + size_t(item) * Db * Kd;
       Qt = Q + (size_t(xp) * md.drd + rd) * Kd * s;
-      wr = li < nbins ? md.Wh[lane_h * md.Wh_sp + hp * md.Wh_sq] : 0.0;
+      wr = li < nbins ? MF<T>::wh(md)[lane_h * md.Wh_sp + hp * md.Wh_sq] : T(0);
     } else {  // item = rho, xp = a'(rho), hp = h(rho)
       Pt = P + size_t(xp + md.da2 * b2) * Da * Db;
       Qt = Q + size_t(item) * Da * s;
-      wr = li < nbins ? md.Wh[hp * md.Wh_sp + lane_h * md.Wh_sq] : 0.0;
+      wr = li < nbins ? MF<T>::wh(md)[hp * md.Wh_sp + lane_h * md.Wh_sq] : T(0);
     }
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
       const bool ok = kk < nkk && k < Kd;
-      pa[kk] = (ok && b < Db) ? Pt[size_t(k) * Db + b] : 0.0;  // [k][b]: 16 consecutive b
+      pa[kk] = (ok && b < Db) ? Pt[size_t(k) * Db + b] : T(0);  // [k][b]: 16 consecutive b
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = j0 + 16 * j + li;
-        qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
+        qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : T(0);
       }
     }
   };
-  v4d acc[4][NJ];
+  typename MF<T>::v4 acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = MF<T>::zero();
   fetch(w);
   for (int t0 = 0; t0 < nitems; t0 += 4) {
     const int t = t0 + w;
-    v4d tt[NJ];
+    typename MF<T>::v4 tt[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) tt[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) tt[j] = MF<T>::zero();
     const bool live = t < nitems;
-    const double wcur = live ? wr : 0.0;
+    const T wcur = live ? wr : T(0);
     if (live) {
 #pragma unroll
       for (int kk = 0; kk < KK; ++kk)
         if (kk < nkk)
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) tt[j] = mfma16(pa[kk], qb[kk][j], tt[j]);
+          for (int j = 0; j < NJ; ++j) tt[j] = MF<T>::mma(pa[kk], qb[kk][j], tt[j]);
     }
     fetch(t + 4);  // next item's operands load during stage 2
     __syncthreads();  // the previous round's stage 2 is done with Ts and Ws
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Ts[w][4 * v + lk][16 * j + li] = tt[j][v];
+      for (int v = 0; v < 4; ++v) Ts[w][MF<T>::row(v, lk)][16 * j + li] = tt[j][v];
     if (lane < 16) Ws[w][lane] = wcur;
     __syncthreads();
-    const double a2 = Ws[lk][li];
+    const T a2 = Ws[lk][li];
 #pragma unroll
     for (int bl = 0; bl < 4; ++bl)
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) acc[bl][j] = mfma16(a2, Ts[lk][4 * w + bl][16 * j + li], acc[bl][j]);
+      for (int j = 0; j < NJ; ++j) acc[bl][j] = MF<T>::mma(a2, Ts[lk][4 * w + bl][16 * j + li], acc[bl][j]);
   }
-  double* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
+  T* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
 #pragma unroll
   for (int bl = 0; bl < 4; ++bl) {
     const int bb = b0 + 4 * w + bl;
@@ -560,7 +588,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
       if (jj >= s) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int h = 4 * v + lk;
+        const int h = MF<T>::row(v, lk);
         if (h < nbins) o[(size_t(h) * Db + bb) * s + jj] = acc[bl][j][v];
       }
     }
@@ -571,12 +599,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
 // (Db <= 32).  P is read as [item][k][row] (16 consecutive rows per load):
 // MODE 0 gets the connector as stored ([l][b][g]), MODE 1 a transposed copy
 // of the MPS site ([sigma][b][a]).
-template <int MODE, int NJ, int VIEW = 0>
-__global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __restrict__ P,
-                                                     const double* __restrict__ Q, int rows, int Db, int Dr2, int s,
-                                                     double* __restrict__ out) {
+template <int MODE, int NJ, int VIEW = 0, class T = double>
+__global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const T* __restrict__ P,
+                                                     const T* __restrict__ Q, int rows, int Db, int Dr2, int s,
+                                                     T* __restrict__ out) {
   constexpr int KK = 8;
-  __shared__ double red[4][16][16 * NJ];
+  __shared__ T red[4][16][16 * NJ];
   const RowGeom::Med& md = f.md;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -638,11 +666,11 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
   }
   // two statically named register buffers (a runtime buffer index would put
   // the arrays in scratch memory)
-  double pa0[KK], qb0[KK][NJ], pa1[KK], qb1[KK][NJ];
-  auto fetch = [&](int t, double (&pa)[KK], double (&qb)[KK][NJ]) {
+  T pa0[KK], qb0[KK][NJ], pa1[KK], qb1[KK][NJ];
+  auto fetch = [&](int t, T (&pa)[KK], T (&qb)[KK][NJ]) {
     if (t >= nitems) return;
-    const double* Pt;
-    const double* Qt;
+    const T* Pt;
+    const T* Qt;
     if (MODE == 0) {
       uint32_t l, bp, hp;
       if (tabbed) {
@@ -665,23 +693,23 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
     for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
       const bool ok = kk < nkk && k < Db;
-      pa[kk] = (ok && row < rows) ? Pt[size_t(k) * rows + row] : 0.0;  // [k][row]: 16 consecutive rows
+      pa[kk] = (ok && row < rows) ? Pt[size_t(k) * rows + row] : T(0);  // [k][row]: 16 consecutive rows
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = j0 + 16 * j + li;
-        qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : 0.0;
+        qb[kk][j] = (ok && jj < s) ? Qt[size_t(k) * s + jj] : T(0);
       }
     }
   };
-  v4d acc[NJ];
+  typename MF<T>::v4 acc[NJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
-  auto use = [&](const double (&pa)[KK], const double (&qb)[KK][NJ]) {
+  for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::zero();
+  auto use = [&](const T (&pa)[KK], const T (&qb)[KK][NJ]) {
 #pragma unroll
     for (int kk = 0; kk < KK; ++kk)
       if (kk < nkk)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[j] = mfma16(pa[kk], qb[kk][j], acc[j]);
+        for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::mma(pa[kk], qb[kk][j], acc[j]);
   };
   fetch(w, pa0, qb0);
   for (int t = w; t < nitems; t += 8) {
@@ -694,9 +722,9 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w][4 * v + lk][16 * j + li] = acc[j][v];
+    for (int v = 0; v < 4; ++v) red[w][MF<T>::row(v, lk)][16 * j + li] = acc[j][v];
   __syncthreads();
-  double* o = out + size_t(MODE == 0 ? ld * md.drd + rd : rho_blk) * rows * s;
+  T* o = out + size_t(MODE == 0 ? ld * md.drd + rd : rho_blk) * rows * s;
   (void)Dr2;
   for (int i = threadIdx.x; i < 16 * 16 * NJ; i += 256) {
     const int r = i / (16 * NJ), jj = i % (16 * NJ);
@@ -715,90 +743,90 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const double* __res
 // One wave per output block for apply (its x range is short); four waves
 // splitting the x range of an output block for applyT, summed through LDS.
 // apply is capped at five waves per SIMD; NJ <= 3 fits that without spilling.
-template <int NJ, int VIEW = 0>
+template <int NJ, int VIEW = 0, class T = double>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
-                                                      uint32_t Bup, uint32_t Bdn, const double* __restrict__ w,
-                                                      const double* __restrict__ A, int Da, int Db,
-                                                      const double* __restrict__ Kc, int Dg,
-                                                      const double* __restrict__ Xt, int s,
-                                                      double* __restrict__ out) {
+                                                      uint32_t Bup, uint32_t Bdn, const T* __restrict__ w,
+                                                      const T* __restrict__ A, int Da, int Db,
+                                                      const T* __restrict__ Kc, int Dg,
+                                                      const T* __restrict__ Xt, int s,
+                                                      T* __restrict__ out) {
   const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
   const uint32_t l = blockIdx.x;
-  v4d acc[NJ];
+  typename MF<T>::v4 acc[NJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::zero();
   for (int f = 0; f < nfree; ++f) {
     const uint32_t x = pdep_dev(l, PL) | pdep_dev(uint32_t(f), FREE);
-    const double wx = w[x];
+    const T wx = w[x];
     if (wx == 0.0) continue;
-    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;  // [b][g]
-    const double* Xu = Xt + size_t(pext_dev(x, Bup)) * Dg * s;  // [g][j]
-    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;  // [a][b]
-    v4d t[NJ];
+    const T* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;  // [b][g]
+    const T* Xu = Xt + size_t(pext_dev(x, Bup)) * Dg * s;  // [g][j]
+    const T* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;  // [a][b]
+    typename MF<T>::v4 t[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) t[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) t[j] = MF<T>::zero();
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       if (4 * kk >= Dg) break;
       const int g = 4 * kk + lk;
-      const double a = (li < Db && g < Dg) ? Kr[li * Dg + g] : 0.0;
+      const T a = (li < Db && g < Dg) ? Kr[li * Dg + g] : T(0);
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = 16 * j + li;
-        t[j] = mfma16(a, (g < Dg && jj < s) ? Xu[size_t(g) * s + jj] : 0.0, t[j]);
+        t[j] = MF<T>::mma(a, (g < Dg && jj < s) ? Xu[size_t(g) * s + jj] : T(0), t[j]);
       }
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int b = 4 * kk + lk;
-      const double a = (li < Da && b < Db) ? wx * Av[li * Db + b] : 0.0;
+      const int b = MF<T>::row(kk, lk);  // chained: item kk is this B row
+      const T a = (li < Da && b < Db) ? wx * Av[li * Db + b] : T(0);
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) acc[j] = mfma16(a, t[j][kk], acc[j]);
+      for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::mma(a, t[j][kk], acc[j]);
     }
   }
-  double* o = out + size_t(l) * Da * s;
+  T* o = out + size_t(l) * Da * s;
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int a = 4 * v + lk, jj = 16 * j + li;
+      const int a = MF<T>::row(v, lk), jj = 16 * j + li;
       if (a < Da && jj < s) o[size_t(a) * s + jj] = acc[j][v];
     }
 }
 
-template <int NJ>
+template <int NJ, class T = double>
 __global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL,
-                                                        uint32_t PR, uint32_t Bdn, const double* __restrict__ w,
-                                                        const double* __restrict__ A, int Da, int Db,
-                                                        const double* __restrict__ Kc, int Dg,
-                                                        const double* __restrict__ Y, int s,
-                                                        double* __restrict__ G) {
-  __shared__ double red[4][32][16 * NJ];
+                                                        uint32_t PR, uint32_t Bdn, const T* __restrict__ w,
+                                                        const T* __restrict__ A, int Da, int Db,
+                                                        const T* __restrict__ Kc, int Dg,
+                                                        const T* __restrict__ Y, int s,
+                                                        T* __restrict__ G) {
+  __shared__ T red[4][32][16 * NJ];
   const int lane = threadIdx.x & 63, w4 = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const uint32_t u = blockIdx.x;
-  v4d acc[2][NJ];
+  typename MF<T>::v4 acc[2][NJ];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[m][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[m][j] = MF<T>::zero();
   for (int f = w4; f < nfree; f += 4) {
     const uint32_t x = pdep_dev(u, Bup) | pdep_dev(uint32_t(f), FREE);
-    const double wx = w[x];
+    const T wx = w[x];
     if (wx == 0.0) continue;
-    const double* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;  // [b][g]
-    const double* Yl = Y + size_t(pext_dev(x, PL)) * Da * s;    // [a][j]
-    const double* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;  // [a][b]
-    v4d t[NJ];
+    const T* Kr = Kc + size_t(pext_dev(x, PR)) * Db * Dg;  // [b][g]
+    const T* Yl = Y + size_t(pext_dev(x, PL)) * Da * s;    // [a][j]
+    const T* Av = A + size_t(pext_dev(x, Bdn)) * Da * Db;  // [a][b]
+    typename MF<T>::v4 t[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) t[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) t[j] = MF<T>::zero();
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {  // T (Db x s) = A^T (Db x Da) . Y (Da x s)
       const int a = 4 * kk + lk;
-      const double av = (li < Db && a < Da) ? Av[a * Db + li] : 0.0;
+      const T av = (li < Db && a < Da) ? Av[a * Db + li] : T(0);
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int jj = 16 * j + li;
-        t[j] = mfma16(av, (a < Da && jj < s) ? Yl[size_t(a) * s + jj] : 0.0, t[j]);
+        t[j] = MF<T>::mma(av, (a < Da && jj < s) ? Yl[size_t(a) * s + jj] : T(0), t[j]);
       }
     }
 #pragma unroll
@@ -807,10 +835,10 @@ __global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t F
       const int g = 16 * m + li;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int b = 4 * kk + lk;
-        const double kv = (g < Dg && b < Db) ? wx * Kr[b * Dg + g] : 0.0;
+        const int b = MF<T>::row(kk, lk);  // chained: item kk is this B row
+        const T kv = (g < Dg && b < Db) ? wx * Kr[b * Dg + g] : T(0);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[m][j] = mfma16(kv, t[j][kk], acc[m][j]);
+        for (int j = 0; j < NJ; ++j) acc[m][j] = MF<T>::mma(kv, t[j][kk], acc[m][j]);
       }
     }
   }
@@ -819,23 +847,14 @@ __global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t F
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[w4][16 * m + 4 * v + lk][16 * j + li] = acc[m][j][v];
+      for (int v = 0; v < 4; ++v) red[w4][16 * m + MF<T>::row(v, lk)][16 * j + li] = acc[m][j][v];
   __syncthreads();
-  double* o = G + size_t(u) * Dg * s;
+  T* o = G + size_t(u) * Dg * s;
   for (int i = threadIdx.x; i < 32 * 16 * NJ; i += 256) {
     const int g = i / (16 * NJ), jj = i % (16 * NJ);
     if (g < Dg && jj < s) o[size_t(g) * s + jj] = red[0][g][jj] + red[1][g][jj] + red[2][g][jj] + red[3][g][jj];
   }
 }
-
-#define TNB_SITE_LAUNCH(NJV, KERNEL, GRID, BLOCK, ST, ...)                                    \
-  switch (NJV) {                                                                             \
-    case 1: hipLaunchKernelGGL((KERNEL<1>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
-    case 2: hipLaunchKernelGGL((KERNEL<2>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
-    case 3: hipLaunchKernelGGL((KERNEL<3>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
-    case 4: hipLaunchKernelGGL((KERNEL<4>), GRID, BLOCK, 0, ST, __VA_ARGS__); break;         \
-    default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");                  \
-  }
 
 // out[n][c][r] = in[n][r][c] for n < count (per-item transpose of r x c blocks)
 __global__ void transpose_blocks_kernel(const double* __restrict__ in, int64_t count, int r, int c,
@@ -846,6 +865,24 @@ __global__ void transpose_blocks_kernel(const double* __restrict__ in, int64_t c
   const int rc = int(idx % (int64_t(r) * c));
   const int i = rc / c, j = rc % c;
   out[(n * c + j) * r + i] = in[idx];
+}
+
+template <class S, class D>
+__global__ void cvt_kernel(const S* __restrict__ in, int64_t n, D* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = D(in[i]);
+}
+
+// out[n][c][r] = in[n][r][c], rounded to D
+template <class D>
+__global__ void transpose_cvt_kernel(const double* __restrict__ in, int64_t count, int r, int c,
+                                     D* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= count * r * c) return;
+  const int64_t n = idx / (int64_t(r) * c);
+  const int rc = int(idx % (int64_t(r) * c));
+  const int i = rc / c, j = rc % c;
+  out[(n * c + j) * r + i] = D(in[idx]);
 }
 
 static size_t medf_bin_lds(int Kd, int nj) {
@@ -930,19 +967,6 @@ static void allow_big_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
 }
 
-#define TNB_NJ_CASE(NJV, KERNEL, MODE, GRID, SHM, ST, ...)                                   \
-  case NJV:                                                                                  \
-    allow_big_lds(KERNEL<MODE, NJV>, SHM);                                                  \
-    hipLaunchKernelGGL((KERNEL<MODE, NJV>), GRID, dim3(256), SHM, ST, __VA_ARGS__);          \
-    break;
-#define TNB_NJ_LAUNCH(NJ, KERNEL, MODE, GRID, SHM, ST, ...)                                    \
-  switch (NJ) {                                                                              \
-    TNB_NJ_CASE(1, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
-    TNB_NJ_CASE(2, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
-    TNB_NJ_CASE(3, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
-    TNB_NJ_CASE(4, KERNEL, MODE, GRID, SHM, ST, __VA_ARGS__)                                 \
-    default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");                   \
-  }
 
 // Copy `width` columns starting at c0 of a row-major (n x lds) matrix into
 // columns d0.. of a row-major (n x ldd) matrix.
@@ -1008,6 +1032,7 @@ struct Zipper {
   DevBuf<double> Om, Y, Qb, Z, Bt, X1, X2, Gs, Vb, Wc, S, VT, connT, SVT, Yf, Cin, Cout;
   // variational refinement: mirrored operands, environments, SVD outputs
   DevBuf<double> Pq, AT, AT2, LT, QU, Mw, Uw, Sw, VTw, L1, C1, Xc;
+  DevBuf<double> cA, cK, cX, cO;  // operands and output of a diagram in FP32 mode (storage only)
   Site phiL;
   std::vector<DevBuf<double>> cn;  // cn[k]: connector / right environment of the box at k-1 (cn[K] = 1)
   std::vector<DevBuf<double>> Lv;  // left environments of the sweeps
@@ -1048,10 +1073,139 @@ struct Zipper {
     }
   }
 
+  // ---- diagram blocks in the precision of the options ----------------------
+  // The FP64 GEMMs that fold bond weights into the operands (W_v, W_dr, W_dl)
+  // and everything outside the diagrams stay FP64; in FP32 mode the diagram
+  // kernels read FP32 copies of their operands and weights and their output
+  // is widened back to FP64.
+  bool f32() const { return o.prec == TNB_F32; }
+
+  template <class T>
+  T* tb(DevBuf<double>& b, size_t n) {
+    ensure(b, (n * sizeof(T) + 7) / 8);
+    return reinterpret_cast<T*>(b.p);
+  }
+  // x as a device operand in T: itself, or a converted copy held in b
+  template <class T>
+  const T* in_T(const double* x, int64_t n, DevBuf<double>& b) {
+    if (sizeof(T) == sizeof(double)) return reinterpret_cast<const T*>(x);
+    T* y = tb<T>(b, size_t(std::max<int64_t>(n, 1)));
+    if (n) hipLaunchKernelGGL((cvt_kernel<double, T>), dim3(blocks(n)), dim3(256), 0, st, x, n, y);
+    return y;
+  }
+  // where a kernel in T writes a result meant for the FP64 array x
+  template <class T>
+  T* out_T(double* x, int64_t n, DevBuf<double>& b) {
+    if (sizeof(T) == sizeof(double)) return reinterpret_cast<T*>(x);
+    return tb<T>(b, size_t(std::max<int64_t>(n, 1)));
+  }
+  template <class T>
+  void back(const T* y, int64_t n, double* x) {
+    if (sizeof(T) == sizeof(double) || n == 0) return;
+    hipLaunchKernelGGL((cvt_kernel<T, double>), dim3(blocks(n)), dim3(256), 0, st, y, n, x);
+  }
+  // out[n][c][r] = in[n][r][c] in T
+  template <class T>
+  T* transposed(const double* in, int64_t count, int r, int c, DevBuf<double>& b) {
+    const int64_t n = count * r * c;
+    T* y = tb<T>(b, size_t(std::max<int64_t>(n, 1)));
+    if (n) hipLaunchKernelGGL((transpose_cvt_kernel<T>), dim3(blocks(n)), dim3(256), 0, st, in, count, r, c, y);
+    return y;
+  }
+  template <class T>
+  static const T* wloc(const RowGeom::Col& c) {
+    return reinterpret_cast<const T*>(sizeof(T) == sizeof(double) ? static_cast<const void*>(c.w)
+                                                                  : static_cast<const void*>(c.w32));
+  }
+#define TNB_TN(name) (sizeof(T) == sizeof(double) ? name : name "_f32")
+
+  // site_apply_mfma for the sketch width s (1 .. 64 columns)
+  template <class T, int VIEW>
+  void launch_site_apply(int s, unsigned grid, uint32_t PL, uint32_t FREE, int nfree, uint32_t PR, uint32_t Bup,
+                         uint32_t Bdn, const T* w, const T* A, int Da, int Db, const T* Kc, int Dg, const T* Xt,
+                         T* out) {
+    switch ((s + 15) / 16) {
+#define TNB_SITE_CASE(NJV)                                                                                  \
+  case NJV:                                                                                                 \
+    hipLaunchKernelGGL((site_apply_mfma<NJV, VIEW, T>), dim3(grid), dim3(64), 0, st, PL, FREE, nfree, PR,  \
+                       Bup, Bdn, w, A, Da, Db, Kc, Dg, Xt, s, out);                                          \
+    break;
+      TNB_SITE_CASE(1)
+      TNB_SITE_CASE(2)
+      TNB_SITE_CASE(3)
+      TNB_SITE_CASE(4)
+#undef TNB_SITE_CASE
+      default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+    }
+  }
+  template <class T>
+  void launch_site_applyT(int s, unsigned grid, uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL, uint32_t PR,
+                          uint32_t Bdn, const T* w, const T* A, int Da, int Db, const T* Kc, int Dg, const T* Y,
+                          T* G) {
+    switch ((s + 15) / 16) {
+#define TNB_SITET_CASE(NJV)                                                                                 \
+  case NJV:                                                                                                 \
+    hipLaunchKernelGGL((site_applyT_mfma<NJV, T>), dim3(grid), dim3(256), 0, st, Bup, FREE, nfree, PL, PR,  \
+                       Bdn, w, A, Da, Db, Kc, Dg, Y, s, G);                                                  \
+    break;
+      TNB_SITET_CASE(1)
+      TNB_SITET_CASE(2)
+      TNB_SITET_CASE(3)
+      TNB_SITET_CASE(4)
+#undef TNB_SITET_CASE
+      default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+    }
+  }
+  // medf_acc_pipe / medf_acc_mfma for NJ = ceil(s / 16)
+  template <int MODE, int VIEW, class T>
+  void launch_acc(bool pipe, int nj, dim3 grid, const MedF& f, const T* P, const T* Q, int rows, int Db, int s,
+                  T* out) {
+    switch (nj) {
+#define TNB_ACC_CASE(NJV)                                                                                        \
+  case NJV:                                                                                                      \
+    if (pipe)                                                                                                    \
+      hipLaunchKernelGGL((medf_acc_pipe<MODE, NJV, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, rows, Db, 0, s, out); \
+    else                                                                                                         \
+      hipLaunchKernelGGL((medf_acc_mfma<MODE, NJV, T>), grid, dim3(256), 0, st, f, P, Q, rows, Db, 0, s, out);   \
+    break;
+      TNB_ACC_CASE(1)
+      TNB_ACC_CASE(2)
+      TNB_ACC_CASE(3)
+      TNB_ACC_CASE(4)
+#undef TNB_ACC_CASE
+      default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+    }
+  }
+  // medf_bin_mfma (LDS-staged, reductions above 32) for NJ = ceil(s / 16)
+  template <int MODE, class T>
+  void launch_bin_mfma(int nj, dim3 grid, size_t shm, const MedF& f, const T* P, const T* Q, int Da, int Db, int Kd,
+                       int s, T* out) {
+    switch (nj) {
+#define TNB_BIN_CASE(NJV)                                                                                    \
+  case NJV:                                                                                                  \
+    allow_big_lds(medf_bin_mfma<MODE, NJV, T>, shm);                                                         \
+    hipLaunchKernelGGL((medf_bin_mfma<MODE, NJV, T>), grid, dim3(256), shm, st, f, P, Q, Da, Db, Kd, s, out); \
+    break;
+      TNB_BIN_CASE(1)
+      TNB_BIN_CASE(2)
+      TNB_BIN_CASE(3)
+      TNB_BIN_CASE(4)
+#undef TNB_BIN_CASE
+      default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+    }
+  }
+
   // D X for site k of row geometry g; X: (ds*Dg) x s, out: (dm*Da) x s
   void apply_block(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* X, int s,
                    double* out) {
+    if (f32()) apply_block_t<float>(g, k, A, Kc, Dg, dm, X, s, out);
+    else apply_block_t<double>(g, k, A, Kc, Dg, dm, X, s, out);
+  }
+  template <class T>
+  void apply_block_t(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* X,
+                     int s, double* out) {
     const int Da = A.dl, Db = A.dr;
+    const double sz = double(sizeof(T));
     if (k % 2 == 0) {
       const auto& c = g.col[k / 2];
       // Xt[u] = sum_v W(v,u) X[v]: (du x Dg*s) = W^T (du x dv) . X (dv x Dg*s)
@@ -1062,21 +1216,25 @@ struct Zipper {
       const uint32_t full = c.k ? ((c.k == 32) ? ~0u : ((1u << c.k) - 1u)) : 0u;
       const uint32_t FREE = full & ~c.PL;
       const int nfree = 1 << popcount32(FREE);
-{
-      KTimer _t("site_apply", st, 2.0 * s * Db * double(Dg + Da) * double(c.dL) * nfree,
-                8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
-                       double(c.dL) * Da * s + double(c.dL) * nfree));
-      if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
-        TNB_SITE_LAUNCH((s + 15) / 16, site_apply_mfma, dim3(c.dL), dim3(64), st, c.PL, FREE, nfree, c.PR, c.Bup,
-                        c.Bdn, c.w, A.data.p, Da, Db, Kc, Dg, Xt, s, out);
-      } else {
-        allow_big_lds(site_apply_kernel, size_t(Db) * s * sizeof(double));
-        hipLaunchKernelGGL(site_apply_kernel, dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(double), st,
-                           k, c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, c.w, A.data.p, Da, Db,
-                           Kc, Dg, Xt, s, out);
-      }
-      HIPC(hipGetLastError());
+      const T* XtT = in_T<T>(Xt, int64_t(c.du) * Dg * s, cX);
+      const T* AT_ = in_T<T>(A.data.p, int64_t(A.size()), cA);
+      const T* KT = in_T<T>(Kc, int64_t(c.dR) * Db * Dg, cK);
+      T* oT = out_T<T>(out, int64_t(c.dL) * Da * s, cO);
+      {
+        KTimer _t(TNB_TN("site_apply"), st, 2.0 * s * Db * double(Dg + Da) * double(c.dL) * nfree,
+                  sz * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
+                        double(c.dL) * Da * s + double(c.dL) * nfree));
+        if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
+          launch_site_apply<T, 0>(s, unsigned(c.dL), c.PL, FREE, nfree, c.PR, c.Bup, c.Bdn, wloc<T>(c), AT_, Da, Db,
+                                  KT, Dg, XtT, oT);
+        } else {
+          allow_big_lds(site_apply_kernel<T>, size_t(Db) * s * sizeof(T));
+          hipLaunchKernelGGL((site_apply_kernel<T>), dim3(c.dL), dim3(256), size_t(Db) * s * sizeof(T), st, k, c.PL,
+                             FREE, nfree, c.PR, c.Bup, c.Bdn, wloc<T>(c), AT_, Da, Db, KT, Dg, XtT, s, oT);
         }
+        HIPC(hipGetLastError());
+      }
+      back<T>(oT, int64_t(c.dL) * Da * s, out);
     } else {
       const auto& md = g.med[(k - 1) / 2];
       ensure(X1, size_t(md.db) * md.dld * Dg * s);
@@ -1089,59 +1247,65 @@ struct Zipper {
       la::gemm(md.dld, md.drd, Dg * s, md.db, la::View{md.Wdl, md.Wdl_sq, md.Wdl_sp, 0},
                la::View{X1.p, int64_t(md.dld) * Dg * s, 1, int64_t(Dg) * s}, X2.p,
                int64_t(Dg) * s, int64_t(md.drd) * Dg * s, 1.0, 0.0, ws, st);
+      const T* X2T = in_T<T>(X2.p, int64_t(md.dld) * md.drd * Dg * s, cX);
       MedF f;
       make_medf(md, &f);
-      ensure(Yf, size_t(md.drd) * md.db2 * f.nHR * Db * s);
+      T* YfT = tb<T>(Yf, size_t(md.drd) * md.db2 * f.nHR * Db * s);
       const int nj = (s + 15) / 16;
       {
-        const size_t shm = medf_bin_lds(Dg, nj);
-        check_lds(shm);
-        KTimer _t1("medf_Y2", st, double(md.drd) * md.dL * (2.0 * Db * Dg * s + 2.0 * f.nHR * Db * s),
-                   8.0 * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
-                          double(md.drd) * md.db2 * f.nHR * Db * s));
+        KTimer _t1(TNB_TN("medf_Y2"), st, double(md.drd) * md.dL * (2.0 * Db * Dg * s + 2.0 * f.nHR * Db * s),
+                   sz * (double(md.dL) * Db * Dg + double(md.dld) * md.drd * Dg * s +
+                         double(md.drd) * md.db2 * f.nHR * Db * s));
         if (Dg <= 32) {
           // one 16-column sketch tile per workgroup keeps the register count
-          // within the kernel's four-waves-per-SIMD cap
-          // the kernel reads the connector as [l][g][b] (contiguous along b)
-          const int64_t nconn = int64_t(md.dL) * Db * Dg;
-          ensure(connT, size_t(nconn));
-          hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nconn)), dim3(256), 0, st, Kc, int64_t(md.dL),
-                             Db, Dg, connT.p);
+          // within the kernel's four-waves-per-SIMD cap; the kernel reads the
+          // connector as [l][g][b] (contiguous along b)
+          const T* cT = transposed<T>(Kc, int64_t(md.dL), Db, Dg, connT);
           const unsigned G = unsigned(md.drd * md.db2 * f.chR);
-          hipLaunchKernelGGL((medf_bin_pipe<0, 1>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0, st, f,
-                             connT.p, X2.p, Da, Db, Dg, s, Yf.p);
+          hipLaunchKernelGGL((medf_bin_pipe<0, 1, 0, T>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0,
+                             st, f, cT, X2T, Da, Db, Dg, s, YfT);
         } else {
-          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, st, f, Kc,
-                        X2.p, Da, Db, Dg, s, Yf.p);
+          const size_t shm = medf_bin_lds(Dg, nj) * sizeof(T) / sizeof(double);
+          check_lds(shm);
+          const T* KT = in_T<T>(Kc, int64_t(md.dL) * Db * Dg, cK);
+          launch_bin_mfma<0, T>(nj, dim3(md.drd * md.db2 * f.chR, (Db + 15) / 16), shm, f, KT, X2T, Da, Db, Dg, s,
+                                YfT);
         }
         HIPC(hipGetLastError());
       }
+      T* oT = out_T<T>(out, int64_t(md.dR) * Da * s, cO);
       {
-        KTimer _t2("medf_out", st, double(md.dR) * md.db2 * 2.0 * Da * Db * s,
-                   8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
-                          double(md.dR) * Da * s));
+        KTimer _t2(TNB_TN("medf_out"), st, double(md.dR) * md.db2 * 2.0 * Da * Db * s,
+                   sz * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
+                         double(md.dR) * Da * s));
         if (Db <= 32) {
           // all sketch columns in one workgroup: the P operand is loaded once;
           // it reads the MPS site transposed, [sigma][b][a]
-          const int64_t nsite = int64_t(A.size());
-          ensure(connT, size_t(nsite));
-          hipLaunchKernelGGL(transpose_blocks_kernel, dim3(blocks(nsite)), dim3(256), 0, st, A.data.p,
-                             int64_t(A.d), Da, Db, connT.p);
-          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, connT.p, Yf.p, Da, Db, 0, s,
-                        out);
+          const T* sT = transposed<T>(A.data.p, int64_t(A.d), Da, Db, connT);
+          launch_acc<1, 0, T>(true, nj, dim3(md.dR, (Da + 15) / 16), f, sT, YfT, Da, Db, s, oT);
         } else {
-          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 1, dim3(md.dR, (Da + 15) / 16), 0, st, f, A.data.p, Yf.p, Da, Db, 0, s,
-                        out);
+          const T* AT_ = in_T<T>(A.data.p, int64_t(A.size()), cA);
+          launch_acc<1, 0, T>(false, nj, dim3(md.dR, (Da + 15) / 16), f, AT_, YfT, Da, Db, s, oT);
         }
         HIPC(hipGetLastError());
       }
+      back<T>(oT, int64_t(md.dR) * Da * s, out);
     }
   }
 
   // D^T Y; Y: (dm*Da) x s, out: (ds*Dg) x s
   void applyT_block(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* Yin, int s,
                     double* out) {
+    if (f32()) applyT_block_t<float>(g, k, A, Kc, Dg, dm, Yin, s, out);
+    else applyT_block_t<double>(g, k, A, Kc, Dg, dm, Yin, s, out);
+  }
+  template <class T>
+  void applyT_block_t(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* Yin,
+                      int s, double* out) {
     const int Da = A.dl, Db = A.dr;
+    const double sz = double(sizeof(T));
+    const T* YT = in_T<T>(Yin, int64_t(dm) * Da * s, cX);
+    const T* AT_ = in_T<T>(A.data.p, int64_t(A.size()), cA);
     if (k % 2 == 0) {
       const auto& c = g.col[k / 2];
       const uint32_t full = c.k ? ((1u << c.k) - 1u) : 0u;
@@ -1149,21 +1313,23 @@ struct Zipper {
       const int nfree = 1 << popcount32(FREE);
       ensure(X1, size_t(c.du) * Dg * s);
       double* G = X1.p;  // du x Dg x s
-{
-      KTimer _t("site_applyT", st, 2.0 * s * Db * double(Dg + Da) * double(c.du) * nfree,
-                8.0 * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
-                       double(c.dL) * Da * s + double(c.du) * nfree));
-      if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
-        TNB_SITE_LAUNCH((s + 15) / 16, site_applyT_mfma, dim3(c.du), dim3(256), st, c.Bup, FREE, nfree, c.PL, c.PR,
-                        c.Bdn, c.w, A.data.p, Da, Db, Kc, Dg, Yin, s, G);
-      } else {
-        allow_big_lds(site_applyT_kernel, size_t(Db) * s * sizeof(double));
-        hipLaunchKernelGGL(site_applyT_kernel, dim3(c.du), dim3(256), size_t(Db) * s * sizeof(double), st,
-                           k, c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, c.w, A.data.p, Da, Db, Kc, Dg,
-                           Yin, s, G);
-      }
-      HIPC(hipGetLastError());
+      T* GT = out_T<T>(G, int64_t(c.du) * Dg * s, cO);
+      const T* KT = in_T<T>(Kc, int64_t(c.dR) * Db * Dg, cK);
+      {
+        KTimer _t(TNB_TN("site_applyT"), st, 2.0 * s * Db * double(Dg + Da) * double(c.du) * nfree,
+                  sz * (double(c.dvd) * Da * Db + double(c.dR) * Db * Dg + double(c.du) * Dg * s +
+                        double(c.dL) * Da * s + double(c.du) * nfree));
+        if (Da <= 16 && Db <= 16 && Dg <= 32 && s <= 64) {
+          launch_site_applyT<T>(s, unsigned(c.du), c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, wloc<T>(c), AT_, Da, Db,
+                                KT, Dg, YT, GT);
+        } else {
+          allow_big_lds(site_applyT_kernel<T>, size_t(Db) * s * sizeof(T));
+          hipLaunchKernelGGL((site_applyT_kernel<T>), dim3(c.du), dim3(256), size_t(Db) * s * sizeof(T), st, k,
+                             c.Bup, FREE, nfree, c.PL, c.PR, c.Bdn, wloc<T>(c), AT_, Da, Db, KT, Dg, YT, s, GT);
         }
+        HIPC(hipGetLastError());
+      }
+      back<T>(GT, int64_t(c.du) * Dg * s, G);
       // out[v] = sum_u W(v,u) G[u]
       la::gemm(1, c.dv, Dg * s, c.du, la::View{c.Wv, c.Wv_sp, c.Wv_sq, 0}, la::View{G, Dg * s, 1, 0},
                out, int64_t(Dg) * s, 0, 1.0, 0.0, ws, st);
@@ -1174,37 +1340,34 @@ struct Zipper {
       double* G2 = X2.p;  // [ld][rd][Dg*s]
       MedF f;
       make_medf(md, &f);
-      ensure(Yf, size_t(md.drd) * md.db2 * f.nHL * Db * s);
+      T* YfT = tb<T>(Yf, size_t(md.drd) * md.db2 * f.nHL * Db * s);
       const int nj = (s + 15) / 16;
       {
-        const size_t shm = medf_bin_lds(Da, nj);
-        check_lds(shm);
-        KTimer _t1("medf_W2", st, double(md.dR) * md.db2 * (2.0 * Da * Db * s + 2.0 * f.nHL * Db * s),
-                   8.0 * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
-                          double(md.drd) * md.db2 * f.nHL * Db * s));
+        KTimer _t1(TNB_TN("medf_W2"), st, double(md.dR) * md.db2 * (2.0 * Da * Db * s + 2.0 * f.nHL * Db * s),
+                   sz * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
+                         double(md.drd) * md.db2 * f.nHL * Db * s));
         if (Da <= 32) {
           const unsigned G = unsigned(md.drd * md.db2 * f.chL);
-          hipLaunchKernelGGL((medf_bin_pipe<1, 1>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0, st, f,
-                             A.data.p, Yin, Da, Db, Da, s, Yf.p);
+          hipLaunchKernelGGL((medf_bin_pipe<1, 1, 0, T>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0,
+                             st, f, AT_, YT, Da, Db, Da, s, YfT);
         } else {
-          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 1, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), shm, st, f, A.data.p,
-                        Yin, Da, Db, Da, s, Yf.p);
+          const size_t shm = medf_bin_lds(Da, nj) * sizeof(T) / sizeof(double);
+          check_lds(shm);
+          launch_bin_mfma<1, T>(nj, dim3(md.drd * md.db2 * f.chL, (Db + 15) / 16), shm, f, AT_, YT, Da, Db, Da, s,
+                                YfT);
         }
         HIPC(hipGetLastError());
       }
+      T* G2T = out_T<T>(G2, int64_t(md.dld) * md.drd * Dg * s, cO);
       {
-        KTimer _t2("medf_G2", st, double(md.dL) * md.drd * 2.0 * Db * Dg * s,
-                   8.0 * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
-                          double(md.dld) * md.drd * Dg * s));
-        if (Db <= 32) {
-          TNB_NJ_LAUNCH(nj, medf_acc_pipe, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, Kc, Yf.p, Dg, Db,
-                        0, s, G2);
-        } else {
-          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 0, dim3(md.dld * md.drd, (Dg + 15) / 16), 0, st, f, Kc, Yf.p, Dg, Db,
-                          0, s, G2);
-        }
+        KTimer _t2(TNB_TN("medf_G2"), st, double(md.dL) * md.drd * 2.0 * Db * Dg * s,
+                   sz * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
+                         double(md.dld) * md.drd * Dg * s));
+        const T* KT = in_T<T>(Kc, int64_t(md.dL) * Db * Dg, cK);
+        launch_acc<0, 0, T>(Db <= 32, nj, dim3(md.dld * md.drd, (Dg + 15) / 16), f, KT, YfT, Dg, Db, s, G2T);
         HIPC(hipGetLastError());
       }
+      back<T>(G2T, int64_t(md.dld) * md.drd * Dg * s, G2);
       // H[ld] (db x Dg*s) = Wdl (db x drd) . G2[ld]
       la::gemm(md.dld, md.db, Dg * s, md.drd, la::View{md.Wdl, md.Wdl_sp, md.Wdl_sq, 0},
                la::View{G2, int64_t(Dg) * s, 1, int64_t(md.drd) * Dg * s}, X1.p, int64_t(Dg) * s,
@@ -1306,84 +1469,76 @@ struct Zipper {
   // One column block of left_cols; Q is the prepared operand (Pt or P2, s columns).
   void left_block(const RowGeom& g, int k, const Site& A, const double* Lin, int t, const double* Q, int s,
                   double* out) {
+    if (f32()) left_block_t<float>(g, k, A, Lin, t, Q, s, out);
+    else left_block_t<double>(g, k, A, Lin, t, Q, s, out);
+  }
+  template <class T>
+  void left_block_t(const RowGeom& g, int k, const Site& A, const double* Lin, int t, const double* Q, int s,
+                    double* out) {
     const int Da = A.dl, Db = A.dr;
+    const double sz = double(sizeof(T));
     if (k % 2 == 0) {
       const auto& c = g.col[k / 2];
       const uint32_t full = c.k ? ((c.k == 32) ? ~0u : ((1u << c.k) - 1u)) : 0u;
       const uint32_t FREE = full & ~c.PR;
       const int nfree = 1 << popcount32(FREE);
-      KTimer _t("site_left", st, 2.0 * s * Da * double(t + Db) * double(c.dR) * nfree,
-                8.0 * (double(c.dvd) * Da * Db + double(c.dL) * Da * t + double(c.du) * t * s +
-                       double(c.dR) * Db * s + double(c.dR) * nfree));
-      // the site chain with P^L and P^R exchanged: A^T (Db x Da), L[l] (Da x t), Pt[u] (t x s)
-      if (Db <= 16 && Da <= 16 && t <= 32 && s <= 64) {
+      const T* QT = in_T<T>(Q, int64_t(c.du) * t * s, cX);
+      const T* LT_ = in_T<T>(Lin, int64_t(c.dL) * Da * t, cK);
+      const T* AT_ = in_T<T>(AT.p, int64_t(A.size()), cA);
+      T* oT = out_T<T>(out, int64_t(c.dR) * Db * s, cO);
+      {
+        KTimer _t(TNB_TN("site_left"), st, 2.0 * s * Da * double(t + Db) * double(c.dR) * nfree,
+                  sz * (double(c.dvd) * Da * Db + double(c.dL) * Da * t + double(c.du) * t * s +
+                        double(c.dR) * Db * s + double(c.dR) * nfree));
+        // the site chain with P^L and P^R exchanged: A^T (Db x Da), L[l] (Da x t), Pt[u] (t x s);
         // VIEW = 1: the same code as the apply, a separate instance so that
         // profiles tell the two uses apart
-        switch ((s + 15) / 16) {
-#define TNB_LEFT_SITE(NJV)                                                                                       \
-  case NJV:                                                                                                      \
-    hipLaunchKernelGGL((site_apply_mfma<NJV, 1>), dim3(c.dR), dim3(64), 0, st, c.PR, FREE, nfree, c.PL, c.Bup,    \
-                       c.Bdn, c.w, AT.p, Db, Da, Lin, t, Q, s, out);                                             \
-    break;
-          TNB_LEFT_SITE(1)
-          TNB_LEFT_SITE(2)
-          TNB_LEFT_SITE(3)
-          TNB_LEFT_SITE(4)
-#undef TNB_LEFT_SITE
-          default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+        if (Db <= 16 && Da <= 16 && t <= 32 && s <= 64) {
+          launch_site_apply<T, 1>(s, unsigned(c.dR), c.PR, FREE, nfree, c.PL, c.Bup, c.Bdn, wloc<T>(c), AT_, Db, Da,
+                                  LT_, t, QT, oT);
+        } else {
+          allow_big_lds(site_apply_kernel<T>, size_t(Da) * s * sizeof(T));
+          hipLaunchKernelGGL((site_apply_kernel<T>), dim3(c.dR), dim3(256), size_t(Da) * s * sizeof(T), st, k, c.PR,
+                             FREE, nfree, c.PL, c.Bup, c.Bdn, wloc<T>(c), AT_, Db, Da, LT_, t, QT, s, oT);
         }
-      } else {
-        allow_big_lds(site_apply_kernel, size_t(Da) * s * sizeof(double));
-        hipLaunchKernelGGL(site_apply_kernel, dim3(c.dR), dim3(256), size_t(Da) * s * sizeof(double), st, k, c.PR,
-                           FREE, nfree, c.PL, c.Bup, c.Bdn, c.w, AT.p, Db, Da, Lin, t, Q, s, out);
+        HIPC(hipGetLastError());
       }
-      HIPC(hipGetLastError());
+      back<T>(oT, int64_t(c.dR) * Db * s, out);
     } else {
       MedF f;
       make_medf(mirror_med(g.med[(k - 1) / 2]), &f);
       const auto& mm = f.md;  // mirrored: "rho" is l, "l" is rho
-      ensure(Yf, size_t(mm.drd) * mm.db2 * f.nHR * Da * s);
+      T* YfT = tb<T>(Yf, size_t(mm.drd) * mm.db2 * f.nHR * Da * s);
+      const T* QT = in_T<T>(Q, int64_t(mm.drd) * mm.dld * t * s, cX);
       const int nj = (s + 15) / 16;
       {
-        KTimer _t1("medf_lbin", st, double(mm.drd) * mm.dL * (2.0 * Da * t * s + 2.0 * f.nHR * Da * s),
-                   8.0 * (double(mm.dL) * Da * t + double(mm.dld) * mm.drd * t * s +
-                          double(mm.drd) * mm.db2 * f.nHR * Da * s));
+        KTimer _t1(TNB_TN("medf_lbin"), st, double(mm.drd) * mm.dL * (2.0 * Da * t * s + 2.0 * f.nHR * Da * s),
+                   sz * (double(mm.dL) * Da * t + double(mm.dld) * mm.drd * t * s +
+                         double(mm.drd) * mm.db2 * f.nHR * Da * s));
         if (t <= 32) {
+          const T* LTT = in_T<T>(LT.p, int64_t(mm.dL) * Da * t, cK);
           const unsigned G = unsigned(mm.drd * mm.db2 * f.chR);
-          hipLaunchKernelGGL((medf_bin_pipe<0, 1, 1>), dim3((G + 7) / 8 * 8 * nj, (Da + 15) / 16), dim3(256), 0, st,
-                             f, LT.p, Q, Db, Da, t, s, Yf.p);
+          hipLaunchKernelGGL((medf_bin_pipe<0, 1, 1, T>), dim3((G + 7) / 8 * 8 * nj, (Da + 15) / 16), dim3(256), 0,
+                             st, f, LTT, QT, Db, Da, t, s, YfT);
         } else {
-          const size_t shm = medf_bin_lds(t, nj);
+          const size_t shm = medf_bin_lds(t, nj) * sizeof(T) / sizeof(double);
           check_lds(shm);
-          TNB_NJ_LAUNCH(nj, medf_bin_mfma, 0, dim3(mm.drd * mm.db2 * f.chR, (Da + 15) / 16), shm, st, f, Lin, Q,
-                        Db, Da, t, s, Yf.p);
+          const T* LinT = in_T<T>(Lin, int64_t(mm.dL) * Da * t, cK);
+          launch_bin_mfma<0, T>(nj, dim3(mm.drd * mm.db2 * f.chR, (Da + 15) / 16), shm, f, LinT, QT, Db, Da, t, s,
+                                YfT);
         }
         HIPC(hipGetLastError());
       }
+      T* oT = out_T<T>(out, int64_t(mm.dR) * Db * s, cO);
       {
-        KTimer _t2("medf_lacc", st, double(mm.dR) * mm.db2 * 2.0 * Db * Da * s,
-                   8.0 * (double(mm.da2) * mm.db2 * Da * Db + double(mm.drd) * mm.db2 * f.nHR * Da * s +
-                          double(mm.dR) * Db * s));
-        if (Da <= 32) {
-          switch (nj) {
-#define TNB_LEFT_ACC(NJV)                                                                                        \
-  case NJV:                                                                                                      \
-    hipLaunchKernelGGL((medf_acc_pipe<1, NJV, 1>), dim3(mm.dR, (Db + 15) / 16), dim3(256), 0, st, f, AT.p, Yf.p,  \
-                       Db, Da, 0, s, out);                                                                       \
-    break;
-            TNB_LEFT_ACC(1)
-            TNB_LEFT_ACC(2)
-            TNB_LEFT_ACC(3)
-            TNB_LEFT_ACC(4)
-#undef TNB_LEFT_ACC
-            default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
-          }
-        } else {
-          TNB_NJ_LAUNCH(nj, medf_acc_mfma, 1, dim3(mm.dR, (Db + 15) / 16), 0, st, f, AT2.p, Yf.p, Db, Da, 0, s,
-                        out);
-        }
+        KTimer _t2(TNB_TN("medf_lacc"), st, double(mm.dR) * mm.db2 * 2.0 * Db * Da * s,
+                   sz * (double(mm.da2) * mm.db2 * Da * Db + double(mm.drd) * mm.db2 * f.nHR * Da * s +
+                         double(mm.dR) * Db * s));
+        const T* AT_ = in_T<T>(Da <= 32 ? AT.p : AT2.p, int64_t(A.size()), cA);
+        launch_acc<1, 1, T>(Da <= 32, nj, dim3(mm.dR, (Db + 15) / 16), f, AT_, YfT, Db, Da, s, oT);
         HIPC(hipGetLastError());
       }
+      back<T>(oT, int64_t(mm.dR) * Db * s, out);
     }
   }
 
@@ -1705,9 +1860,10 @@ extern "C" tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opt
     if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
     if (!opts || opts->chi < 1 || opts->chi > 64 || opts->sketch_extra < 0 || opts->sketch_extra > 64 ||
         opts->power_iters < 0 || opts->power_iters > 8 || !(opts->cut >= 1e-7) || !(opts->cut < 1.0) ||
-        (opts->var_window != 0 && opts->var_window != 2) || opts->var_sweeps < 0 || opts->var_sweeps > 8)
+        (opts->var_window != 0 && opts->var_window != 2) || opts->var_sweeps < 0 || opts->var_sweeps > 8 ||
+        (opts->prec != TNB_F64 && opts->prec != TNB_F32))
       fail(TNB_EINVAL, "options out of range (1 <= chi <= 64, 0 <= extra <= 64, 0 <= power <= 8, 1e-7 <= cut < 1, "
-                       "var_window 0 or 2, 0 <= var_sweeps <= 8)");
+                       "var_window 0 or 2, 0 <= var_sweeps <= 8, prec TNB_F64 or TNB_F32)");
     hipStream_t st = static_cast<hipStream_t>(stream);
     auto env = std::make_unique<tnb_env>();
     env->cl = cl;
@@ -1821,13 +1977,14 @@ extern "C" tnb_status tnb_diagram_dims(const tnb_clusters* cl, int32_t r, int32_
   });
 }
 
-extern "C" tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32_t mode,
+extern "C" tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32_t mode, int32_t prec,
                                         const double* d_A, int32_t Da, int32_t Db, const double* d_K, int32_t Dg,
                                         const double* d_X, int32_t s, double* d_out, int64_t out_len,
                                         tnb_stream stream) {
   return guarded([&] {
     if (!cl || cl->kind != KIND_CLUSTERS) fail(TNB_EINVAL, "not a clusters handle");
     if (mode < 0 || mode > 2) fail(TNB_EINVAL, "mode must be 0 (apply), 1 (transpose) or 2 (left transfer)");
+    if (prec != TNB_F64 && prec != TNB_F32) fail(TNB_EINVAL, "prec must be TNB_F64 or TNB_F32");
     if (Da < 1 || Db < 1 || Dg < 1 || s < 1 || Da > 128 || Db > 128 || Dg > 128 || s > 256)
       fail(TNB_EINVAL, "bond dimensions out of range (1 .. 128; s 1 .. 256)");
     if (!d_A || !d_K || !d_X || !d_out) fail(TNB_EINVAL, "NULL tensor");
@@ -1839,6 +1996,7 @@ extern "C" tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32
     tnb_env_opts o{};
     o.chi = 1;
     o.cut = 1e-7;
+    o.prec = prec;
     la::Scratch ws;
     Zipper z{cl, o, ws, st};
     const RowGeom g = row_geom(cl, r);

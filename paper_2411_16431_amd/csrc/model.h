@@ -15,6 +15,7 @@ struct tnb_clusters {
   // local tables, concatenated over clusters
   std::vector<int64_t> loc_off;
   tnb::DevBuf<double> E_loc, w_loc;
+  tnb::DevBuf<float> w_loc32;  // the weights rounded to FP32 (FP32 contractions)
   std::vector<double> E_min_loc;
   // bond tables of unordered neighbour pairs m < n, [p of m][q of n]
   struct Bond {
@@ -26,6 +27,7 @@ struct tnb_clusters {
   std::vector<Bond> bonds;
   std::map<int64_t, int> bond_of;  // m*cells + n (m < n) -> index
   tnb::DevBuf<double> E_bond, W_bond;
+  tnb::DevBuf<float> W_bond32;
   double shift = 0.0;  // sum over all tables of -beta * min energy
   // the instance on the device (energies of returned states, Eq. 1)
   tnb::DevBuf<int32_t> d_ei, d_ej;
@@ -51,5 +53,13 @@ struct tnb_clusters {
     if (m < n) { *sp = bd.cols; *sq = 1; }
     else { *sp = 1; *sq = bd.cols; }
     return true;
+  }
+  // The FP32 copy of the same table, same strides.
+  const float* weight32(int m, int n) const {
+    if (m < 0 || n < 0) return nullptr;
+    int a = m < n ? m : n, b = m < n ? n : m;
+    auto it = bond_of.find(int64_t(a) * lat.cells() + b);
+    if (it == bond_of.end()) return nullptr;
+    return W_bond32.p + bonds[it->second].off;
   }
 };
