@@ -25,6 +25,11 @@ WORKLOADS = {
     # beta = 1, chi = 16, beam M = 64, 8 states returned, FP64.
     "zephyr_z2_t4_plain": dict(kind="zephyr", kw=dict(m=2, t=4), seed=1000, jdist="uniform",
                                hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
+    # App. B workload: king's lattice 50 x 50 with one spin per site (d = 2),
+    # tile-planted so that the exact ground energy E0 is known; beta = 4,
+    # chi = 16, M = 256
+    "king_50x50_planted": dict(kind="king_planted", kw=dict(R=50, C=50, a=1), seed=1000, jdist="planted",
+                               hdist="zero", beta=4.0, chi=16, M=256, K=8),
     # small sibling used for quick checks (t = 2 cells of 8 spins)
     "zephyr_z2_t2_plain": dict(kind="zephyr", kw=dict(m=2, t=2), seed=1000, jdist="uniform",
                                hdist="uniform0.1", beta=1.0, chi=16, M=64, K=8),
@@ -150,8 +155,12 @@ def parse():
 
 
 def make(wl):
-    from tnb_inputs import make_instance
-    return make_instance(wl["kind"], wl["seed"], jdist=wl["jdist"], hdist=wl["hdist"], **wl["kw"])
+    """The workload's instance, and its exact ground energy when planted (else None)."""
+    from tnb_inputs import make_instance, planted_king
+    if wl["kind"] == "king_planted":
+        inst, _, E0 = planted_king(wl["kw"]["R"], wl["kw"]["C"], wl["kw"]["a"], wl["seed"], loops_per_cell=1)
+        return inst, E0
+    return make_instance(wl["kind"], wl["seed"], jdist=wl["jdist"], hdist=wl["hdist"], **wl["kw"]), None
 
 
 def cpu_baseline(inst, wl, counts, marg_per_step, power):
@@ -203,6 +212,22 @@ def cpu_baseline(inst, wl, counts, marg_per_step, power):
               (t_site, n_sl, full_dR, t_med, site_calls, med_calls))
     return dict(value=marg_per_step / t_step, unit="spin marginals/s", cores=int(threads),
                 kind="oracle", sample=sample, seconds_per_step_extrapolated=t_step)
+
+
+def cpu_baseline_full(inst, wl, marg_per_step):
+    """Oracle end to end on the same instance (feasible for d = 2 clusters):
+    all boundary MPSs and the whole beam search, timed on the host cores."""
+    from threadpoolctl import threadpool_info
+    from oracle.bmps import contract_env, Options
+    from oracle.search import solve
+    t0 = time.perf_counter()
+    env = contract_env(inst, wl["beta"], Options(chi=wl["chi"], power=2, seed=4242))
+    ref = solve(inst, wl["beta"], env, M=wl["M"], K=wl["K"])
+    dt = time.perf_counter() - t0
+    threads = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas") or 1
+    return dict(value=marg_per_step / dt, unit="spin marginals/s", cores=int(threads), kind="oracle",
+                sample="oracle contract_env and solve end to end on the benchmark instance (%.1f s)" % dt,
+                seconds_per_step=dt), float(ref["energies"][0]), env.logZ
 
 
 def adjoint_compare(pk, torch, env, wl, inst):
@@ -290,7 +315,7 @@ def main():
     torch.cuda.set_device(0)
     import paper_2411_16431_amd as pk
     wl = WORKLOADS[args.workload]
-    inst = make(wl)
+    inst, E0 = make(wl)
     env_kw = dict(power_iters=args.power_iters, seed=4242)
 
     def one():
@@ -334,11 +359,19 @@ def main():
     adj = adjoint_compare(pk, torch, res["env"], wl, inst)
     f32 = None if args.no_f32 else fp32_compare(pk, torch, inst, wl, env_kw, res, args.steps)
     print("fp32 comparison done", file=sys.stderr, flush=True)
-    planted = None if args.no_planted else planted_gap(pk, wl, env_kw)
+    planted = None if (args.no_planted or E0 is not None) else planted_gap(pk, wl, env_kw)
     print("adjoint comparison done", file=sys.stderr, flush=True)
-    cpu = None
+    cpu, gap_oracle, exact = None, None, None
+    best = float(res["energies"][0])
+    if E0 is not None:
+        exact = {"E0": float(E0), "best_energy": best, "d_E": (best - E0) / (2 * abs(E0))}
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inst, wl, counts, marg, args.power_iters)
+        if wl["kind"] == "king_planted":
+            cpu, e_ora, z_ora = cpu_baseline_full(inst, wl, marg)
+            gap_oracle = {"oracle_best_energy": e_ora, "d_E": (best - e_ora) / (2 * abs(e_ora)),
+                          "oracle_logZ": z_ora, "logZ_rel_diff": abs(res["logZ"] - z_ora) / abs(z_ora)}
+        else:
+            cpu = cpu_baseline(inst, wl, counts, marg, args.power_iters)
     out = {
         "metric": "beam marginals/sec and best energy gap vs oracle, adjoint+batched vs plain",
         "value": value, "unit": "spin marginals/s", "n_gpus": 1, "steps": args.steps,
@@ -348,7 +381,8 @@ def main():
                    "lattice": [int(inst.R), int(inst.C)], "beta": wl["beta"], "chi": wl["chi"],
                    "beam_M": wl["M"], "returned_K": wl["K"], "mode": "plain (per-step marginals, no adjoint)",
                    "power_iters": args.power_iters},
-        "best_energy": float(res["energies"][0]), "energy_gap_vs_oracle": None, "energy_gap_planted": planted,
+        "best_energy": best, "energy_gap_vs_oracle": gap_oracle, "energy_gap_exact": exact,
+        "energy_gap_planted": planted,
         "logZ": res["logZ"], "spin_marginals_per_step": marg,
         "roofline": roof, "cpu_baseline": cpu, "adjoint": adj, "fp32": f32,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},

@@ -229,6 +229,16 @@ tnb_status tnb_beam_export(const tnb_beam* beam, int32_t K, int8_t* d_states, do
 tnb_status tnb_beam_lowest(tnb_beam* beam, int32_t K, int8_t* d_states, double* d_E, int32_t* count,
                            tnb_stream stream);
 
+/* The same selection over caller arrays: the K lowest distinct of n
+ * configurations d_states (device, int8 [n][n_spins] of +-1) with energies
+ * d_E (device, [n]), ordered as in tnb_beam_lowest, into d_out ([K][n_spins])
+ * and d_E_out ([K]); *count (host, may be NULL) = min(K, distinct).  Used to
+ * pool the results of several runs, e.g. the eight lattice transformations
+ * of Sec. V.A.  Synchronises `stream`.  Errors: TNB_EINVAL (sizes, NULL
+ * pointers). */
+tnb_status tnb_select_lowest(const int8_t* d_states, const double* d_E, int64_t n, int32_t n_spins,
+                             int32_t K, int8_t* d_out, double* d_E_out, int32_t* count, tnb_stream stream);
+
 /* Layout of the row moments at the current step n = (r, c): the spins of
  * the unfixed clusters (r, c) .. (r, cols-1), cluster by cluster in
  * ascending spin index, and the couplings with both ends in one of those

@@ -184,6 +184,18 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
                 pd_log = max(pd_log, sc[win[M]])
             rec = dict(n=n, candidates=len(bb), groups=len(win), kept=len(keep))
             if trace:
+                # selection margins (R7, R10): the score gap between the last
+                # kept group and the first dropped one, and the smallest gap
+                # between a group's winner and its runner-up
+                rec["boundary_gap"] = sc[win[M - 1]] - sc[win[M]] if len(win) > M else np.inf
+                if merge and masks and len(bb) > len(win):
+                    ordk = np.lexsort((-sc,) + tuple(keys[:, i] for i in range(keys.shape[1] - 1, -1, -1)))
+                    ks, ss = keys[ordk], sc[ordk]
+                    same = np.all(ks[1:] == ks[:-1], axis=1)
+                    head = same & np.r_[True, ~same[:-1]]      # winner and runner-up of a group
+                    rec["group_gap"] = float(np.min((ss[:-1] - ss[1:])[head])) if head.any() else np.inf
+                else:
+                    rec["group_gap"] = np.inf
                 rec["p"] = np.where(alive[:, None], qpos / np.where(alive, Zb, 1.0)[:, None], 0.0)
                 rec["X"] = X[bb[keep]].copy()
                 rec["X"][:, n] = xx[keep]

@@ -41,6 +41,8 @@ SIGNATURES = {
     "tnb_branch_step": (c_int32, [c_void_p, P(c_double), c_void_p]),
     "tnb_beam_export": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_beam_lowest": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
+    "tnb_select_lowest": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, P(c_int32),
+                                    c_void_p]),
     "tnb_row_layout": (c_int32, [c_void_p, P(c_int32), P(c_int32), c_void_p, c_void_p, c_int32]),
     "tnb_row_moments": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
     "tnb_row_moments_per_branch": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),

@@ -282,6 +282,41 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
                 beam=beam, spin_marginals=marg)
 
 
+def select_lowest(states, E, K):
+    """tnb_select_lowest on cuda tensors: the K lowest distinct of the given
+    configurations (int8 [n, N]) and energies ([n]), by energy then spin vector."""
+    import torch
+    n, N = states.shape
+    out = torch.empty((max(K, 1), N), dtype=torch.int8, device=states.device)
+    Eo = torch.empty(max(K, 1), dtype=torch.float64, device=states.device)
+    cnt = ctypes.c_int32()
+    _check(L.lib().tnb_select_lowest(ctypes.c_void_p(states.data_ptr()), ctypes.c_void_p(E.data_ptr()), int(n),
+                                     int(N), int(K), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(Eo.data_ptr()),
+                                     ctypes.byref(cnt), _stream()))
+    return out[:cnt.value], Eo[:cnt.value]
+
+
+def solve_transformed(inst, beta, chi, M, K=8, transforms=range(8), **env_kw):
+    """The method on each lattice symmetry of the instance (Sec. V.A: the
+    search runs row by row in a fixed direction, so the eight orientations of
+    the cluster lattice give different approximations), with the K lowest
+    distinct states pooled over all runs.  Returns the pooled states and
+    energies, log Z per transformation and its spread (max - min, zero for an
+    exact contraction), and each run's best energy."""
+    import torch
+    from tnb_inputs import transform
+    S, E, logz, best = [], [], {}, {}
+    for t in transforms:
+        res = solve(transform(inst, t), beta, chi, M, K, **env_kw)
+        S.append(torch.from_numpy(res["states"]).cuda())
+        E.append(torch.from_numpy(res["energies"]).cuda())
+        logz[t], best[t] = res["logZ"], float(res["energies"][0])
+    st, en = select_lowest(torch.cat(S).contiguous(), torch.cat(E).contiguous(), K)
+    vals = list(logz.values())
+    return dict(states=st.cpu().numpy(), energies=en.cpu().numpy(), logZ=logz, logZ_spread=max(vals) - min(vals),
+                best_energy=best)
+
+
 def first_row_layout(inst, beta=1.0):
     """(spins, edges) of the first row of clusters: the inputs of FirstRowLogZ."""
     env = Env(Clusters(inst, beta), EnvOptions(chi=1))

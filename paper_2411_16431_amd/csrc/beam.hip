@@ -959,6 +959,30 @@ extern "C" tnb_status tnb_beam_lowest(tnb_beam* bm, int32_t K, int8_t* d_states,
   });
 }
 
+extern "C" tnb_status tnb_select_lowest(const int8_t* d_states, const double* d_E, int64_t n, int32_t n_spins,
+                                        int32_t K, int8_t* d_out, double* d_E_out, int32_t* count,
+                                        tnb_stream stream) {
+  return guarded([&] {
+    if (n < 0 || n > (int64_t(1) << 30) || n_spins < 1 || K < 0) fail(TNB_EINVAL, "bad sizes");
+    if (n > 0 && (!d_states || !d_E)) fail(TNB_EINVAL, "NULL input");
+    if (K > 0 && n > 0 && (!d_out || !d_E_out)) fail(TNB_EINVAL, "NULL output");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int found = 0;
+    if (n > 0 && K > 0) {
+      DevBuf<int> dup{static_cast<size_t>(n)};
+      hipLaunchKernelGGL(sel_dup_kernel, dim3(unsigned(n)), dim3(256), 0, st, d_states, d_E, int(n), n_spins, dup.p);
+      hipLaunchKernelGGL(sel_rank_kernel, dim3(unsigned(n)), dim3(256), 0, st, d_states, d_E, dup.p, int(n), n_spins, K,
+                         d_out, d_E_out);
+      HIPC(hipGetLastError());
+      std::vector<int> h(static_cast<size_t>(n));
+      HIPC(hipMemcpyAsync(h.data(), dup.p, size_t(n) * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      for (int v : h) found += v ? 0 : 1;
+    }
+    if (count) *count = std::min<int64_t>(K, found);
+  });
+}
+
 extern "C" void tnb_destroy(void* handle) {
   if (!handle) return;
   uint32_t kind = *static_cast<uint32_t*>(handle);

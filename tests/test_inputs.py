@@ -49,3 +49,15 @@ def test_planted_energy_is_sum_of_loop_minima():
     inst, s, E0 = planted_loops(2, 4, 5000)
     H = float(np.sum(inst.J * s[inst.edges[:, 0]] * s[inst.edges[:, 1]]))
     assert H == E0 and E0 < 0
+
+
+def test_planted_king_ground_energy():
+    # App. B workload stand-in: one spin per site; s* attains E0, and on a
+    # lattice small enough for brute force E0 is the ground energy
+    import numpy as np
+    from tnb_inputs import planted_king
+    from oracle import ising
+    inst, s, E0 = planted_king(4, 4, 1, 7, loops_per_cell=1)
+    assert ising.brute_force(inst, 1.0)["E_min"] == E0
+    big, s_big, E0_big = planted_king(50, 50, 1, 7, loops_per_cell=1)
+    assert big.n_spins == 2500 and ising.energies(big, s_big[None].astype(np.int8))[0] == E0_big

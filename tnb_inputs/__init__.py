@@ -7,8 +7,9 @@ arrays.
 """
 from .rng import splitmix64, uniform01
 from .geometry import zephyr_graph, zephyr_cross_cells, king_lattice, chain_lattice
-from .instances import Instance, make_instance, random_couplings, planted_loops
+from .instances import (Instance, make_instance, random_couplings, planted_loops, planted_king, transform, transform_cells,
+                        N_TRANSFORMS)
 
 __all__ = ["splitmix64", "uniform01", "zephyr_graph", "zephyr_cross_cells",
            "king_lattice", "chain_lattice", "Instance", "make_instance",
-           "random_couplings", "planted_loops"]
+           "random_couplings", "planted_loops", "planted_king", "transform", "transform_cells", "N_TRANSFORMS"]

@@ -23,6 +23,45 @@ class Instance:
         return self.R * self.C
 
 
+# The eight symmetries of the R x C cluster lattice (Sec. V.A): the search and
+# the boundary MPSs always run rows top to bottom and columns left to right,
+# so relabelling the cluster positions changes the order in which the method
+# meets the clusters, and with it the approximation, but not the instance.
+# Transformation t = 4 f + q: q quarter turns clockwise, then a left-right
+# mirror when f = 1.
+N_TRANSFORMS = 8
+
+
+def transform_cells(R, C, t):
+    """(R', C', map) with map(r, c) -> (r', c') for transformation t (0..7)."""
+    if not 0 <= t < N_TRANSFORMS:
+        raise ValueError("t must be in 0..7")
+    q, f = t % 4, t // 4
+
+    def turn(r, c, R, C):            # one quarter turn clockwise
+        return c, R - 1 - r, C, R
+    def f_map(r, c):
+        RR, CC = R, C
+        for _ in range(q):
+            r, c, RR, CC = turn(r, c, RR, CC)
+        if f:
+            c = CC - 1 - c
+        return r, c
+    RR, CC = (R, C) if q % 2 == 0 else (C, R)
+    return RR, CC, f_map
+
+
+def transform(inst, t):
+    """The same instance (spins, couplings, fields) with its clusters placed by
+    lattice symmetry t; t = 0 is the identity."""
+    R2, C2, f = transform_cells(inst.R, inst.C, t)
+    r, c = np.divmod(np.asarray(inst.cell_of, dtype=np.int64), inst.C)
+    r2, c2 = f(r, c)
+    cell = np.asarray(r2, dtype=np.int64) * C2 + np.asarray(c2, dtype=np.int64)
+    meta = dict(inst.meta, transform=t)
+    return Instance(inst.n_spins, inst.edges, inst.J, inst.h, R2, C2, cell, meta)
+
+
 def random_couplings(n_edges, n_spins, seed, jdist="uniform", hdist="zero"):
     """Class I / II draws: J ~ U[-1,1] (or {+-1..+-4}/4), h ~ U[-0.1,0.1] or 0."""
     if jdist == "uniform":
@@ -101,6 +140,22 @@ def planted_loops(m, t, seed, loops_per_cell=3):
     """
     n, e = G.zephyr_graph(m, t)
     R, C, cell_of = G.zephyr_cross_cells(m, t)
+    return planted_on_graph(n, e, R, C, cell_of, seed, loops_per_cell,
+                            dict(kind="zephyr_planted", m=m, t=t, seed=seed))
+
+
+def planted_king(R, C, a, seed, loops_per_cell=2):
+    """The same tile planting on a king's lattice of a x a spin blocks (the
+    square / king's-lattice workload of App. B has one spin per site, a = 1).
+    Returns (instance, s_star, E0)."""
+    (n, e), (R2, C2, cell_of) = G.king_lattice(R, C, a, True)
+    return planted_on_graph(n, e, R2, C2, cell_of, seed, loops_per_cell,
+                            dict(kind="king_planted", R=R, C=C, a=a, seed=seed))
+
+
+def planted_on_graph(n, e, R, C, cell_of, seed, loops_per_cell, meta):
+    """Frustrated loops planted around a hidden s* (see planted_loops) on any
+    clustered graph; E0 = sum over loops of (1.5 - L)."""
     s_star = np.where(integers(seed, n, 7, 2) == 1, 1, -1).astype(np.int64)
     adj = [set() for _ in range(n)]
     for a, b in e:
@@ -140,5 +195,5 @@ def planted_loops(m, t, seed, loops_per_cell=3):
                 J[k] += (0.5 * sgn) if q == weak else (-1.0 * sgn)
             E0 += 1.5 - L
     h = np.zeros(n)
-    inst = Instance(n, e, J, h, R, C, cell_of, dict(kind="zephyr_planted", m=m, t=t, seed=seed))
+    inst = Instance(n, e, J, h, R, C, cell_of, meta)
     return inst, s_star, E0
