@@ -190,15 +190,22 @@ tnb_status tnb_beam_create(tnb_env* env, int32_t M, tnb_beam** out);
  * and the size d of the next cluster; any pointer may be NULL. */
 tnb_status tnb_beam_info(const tnb_beam* beam, int32_t* step, int32_t* n_parents, int32_t* d);
 
-/* Conditional marginals p(x_{n+1} | boundary of parent b) for every parent
- * of the current step (Eq. 7, 9; Fig. 6b): d_out (device) receives
- * [n_parents][d] probabilities, normalised per parent.  The marginal is a
- * ratio of contractions of one network, so a common sign of the approximate
- * environment cancels: entries are taken with the sign of their sum, and
- * those left non-positive are clipped to 0.  out_len must be >= n_parents*d.
- * Errors: TNB_EINVAL (size), TNB_ENUMERIC (a parent with no positive
- * marginal; it is reported, not dropped, by this call). */
-tnb_status tnb_marginals(tnb_beam* beam, double* d_out, int64_t out_len, tnb_stream stream);
+/* Marginals of every parent b of the current step, in one of three forms:
+ *  TNB_MARG_VECTOR: the conditional distribution p(x_{n+1} | boundary of b)
+ *    of the next cluster (Eq. 7, 9; Fig. 6b), [n_parents][d], normalised per
+ *    parent.  The marginal is a ratio of contractions of one network, so a
+ *    common sign of the approximate environment cancels: entries are taken
+ *    with the sign of their sum, and those left non-positive are clipped to 0.
+ *  TNB_MARG_SPIN: <s_i>_b = sum_x p(x | b) s_i(x) for the k spins of the next
+ *    cluster (bit order), [n_parents][k].
+ *  TNB_MARG_ADJOINT: <s_i>_b of every spin of the unfixed clusters of the
+ *    current row by the adjoint sweep, [n_parents][n_spins of tnb_row_layout]
+ *    (the d_m1 output of tnb_row_moments).
+ * out_len is d_out's capacity in doubles.  Synchronises `stream`.
+ * Errors: TNB_EINVAL (mode, size), TNB_ENUMERIC (a parent with no positive
+ * marginal, or a zero row contraction; reported, not dropped). */
+typedef enum { TNB_MARG_VECTOR = 0, TNB_MARG_SPIN = 1, TNB_MARG_ADJOINT = 2 } tnb_marg_mode;
+tnb_status tnb_marginals(tnb_beam* beam, int32_t mode, double* d_out, int64_t out_len, tnb_stream stream);
 
 /* One branch-and-bound step (Fig. 3): branch every parent over all d values
  * of the next cluster, score with the chain rule (Eq. 7) in log space, keep

@@ -37,7 +37,7 @@ SIGNATURES = {
                                     c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
     "tnb_beam_create": (c_int32, [c_void_p, c_int32, P(c_void_p)]),
     "tnb_beam_info": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),
-    "tnb_marginals": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "tnb_marginals": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p]),
     "tnb_branch_step": (c_int32, [c_void_p, P(c_double), c_void_p]),
     "tnb_beam_export": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_beam_lowest": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),

@@ -113,6 +113,7 @@ class Clusters(_Handle):
 
 
 PRECS = {"f64": 0, "f32": 1}
+MARG_MODES = {"vector": 0, "spin": 1, "adjoint": 2}
 
 
 @dataclass
@@ -164,12 +165,22 @@ class Beam(_Handle):
         _check(L.lib().tnb_beam_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
-    def marginals(self):
+    def marginals(self, mode="vector"):
+        """tnb_marginals: 'vector' p_b(x) [parents, d]; 'spin' <s_i>_b of the
+        next cluster [parents, k]; 'adjoint' <s_i>_b of the unfixed row spins
+        [parents, len(row_layout()[0])]."""
         import torch
         _, npar, d = self.info()
-        out = torch.empty((npar, d), dtype=torch.float64, device="cuda")
-        _check(L.lib().tnb_marginals(self._h, ctypes.c_void_p(out.data_ptr()), out.numel(), _stream()))
-        return out
+        if mode == "vector":
+            cols = d
+        elif mode == "spin":
+            cols = int(round(math.log2(d)))
+        else:
+            cols = len(self.row_layout()[0])
+        out = torch.empty((npar, max(cols, 1)), dtype=torch.float64, device="cuda")
+        _check(L.lib().tnb_marginals(self._h, MARG_MODES[mode], ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                     _stream()))
+        return out[:, :cols]
 
     def step(self):
         pd = ctypes.c_double()

@@ -485,6 +485,25 @@ __global__ void export_kernel(const int32_t* __restrict__ X, int ncell, int nfix
   if (lp_out && j == 0) lp_out[i] = logp[i];
 }
 
+// <s_i>_b = sum_x p_b(x) s_i(x) for bit i of the cluster (blockIdx.y), parent
+// b = blockIdx.x; s_i(x) = +1 when bit i of x is set.
+__global__ void spin_moment_kernel(const double* __restrict__ P, int64_t d, int k, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, i = blockIdx.y;
+  double acc = 0.0;
+  for (int64_t x = threadIdx.x; x < d; x += blockDim.x) {
+    const double p = P[b * d + x];
+    acc += ((x >> i) & 1) ? p : -p;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[int64_t(b) * k + i] = red[0];
+}
+
 // Final selection (the K lowest distinct states).  Candidate j precedes i
 // when its energy is lower, or equal with a spin vector that is smaller
 // lexicographically (spin 0 first, -1 < +1).
@@ -756,13 +775,25 @@ extern "C" tnb_status tnb_beam_info(const tnb_beam* bm, int32_t* step, int32_t* 
   });
 }
 
-extern "C" tnb_status tnb_marginals(tnb_beam* bm, double* d_out, int64_t out_len, tnb_stream stream) {
+extern "C" tnb_status tnb_row_moments(tnb_beam* bm, double* d_m1, int64_t m1_len, double* d_m2, int64_t m2_len,
+                                      tnb_stream stream);
+
+extern "C" tnb_status tnb_marginals(tnb_beam* bm, int32_t mode, double* d_out, int64_t out_len, tnb_stream stream) {
+  if (mode == TNB_MARG_ADJOINT) return tnb_row_moments(bm, d_out, out_len, nullptr, 0, stream);
   return guarded([&] {
     if (!bm || bm->kind != KIND_BEAM) fail(TNB_EINVAL, "not a beam handle");
+    if (mode != TNB_MARG_VECTOR && mode != TNB_MARG_SPIN) fail(TNB_EINVAL, "unknown marginal mode");
     if (bm->step >= bm->ncell) fail(TNB_EINVAL, "every cluster is fixed");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t d = int64_t(1) << bm->env->cl->lat.k[bm->step];
-    if (!d_out || out_len < bm->npar * d) fail(TNB_EINVAL, "output too small");
+    const int kbits = bm->env->cl->lat.k[bm->step];
+    const int64_t d = int64_t(1) << kbits;
+    const int64_t need = mode == TNB_MARG_VECTOR ? bm->npar * d : int64_t(bm->npar) * kbits;
+    if (!d_out || out_len < need) fail(TNB_EINVAL, "output too small");
+    double* P = d_out;
+    if (mode == TNB_MARG_SPIN) {
+      ensure(bm->U, size_t(bm->npar) * d);  // p_b(x) before the moments
+      P = bm->U.p;
+    }
     compute_q(bm, st);
     if (std::getenv("TNB_DEBUG")) {
       std::vector<double> hq(std::min<int64_t>(d, 4));
@@ -779,8 +810,11 @@ extern "C" tnb_status tnb_marginals(tnb_beam* bm, double* d_out, int64_t out_len
       }
     }
     HIPC(hipMemsetAsync(bm->dead.p, 0, sizeof(int), st));
-    hipLaunchKernelGGL(beam_score_kernel, dim3(bm->npar), dim3(256), 0, st, bm->q.p, d, bm->logp.p, nullptr, d_out,
+    hipLaunchKernelGGL(beam_score_kernel, dim3(bm->npar), dim3(256), 0, st, bm->q.p, d, bm->logp.p, nullptr, P,
                        bm->dead.p);
+    if (mode == TNB_MARG_SPIN && kbits > 0)
+      hipLaunchKernelGGL(spin_moment_kernel, dim3(bm->npar, kbits), dim3(256), 0, st, P, d, kbits, d_out);
+    HIPC(hipGetLastError());
     int dead = 0;
     HIPC(hipMemcpyAsync(&dead, bm->dead.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));

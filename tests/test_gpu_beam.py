@@ -41,6 +41,8 @@ def test_stepwise_beam_matches_oracle(kind, kw, chi, M):
         err = np.abs(p - rec["p"]).max()
         assert err <= 1e-5, "marginals differ at step %d (max |dp| = %g)" % (rec["n"], err)
         pd = beam.step()
+        # largest discarded probability so far (Sec. III.A), as the oracle
+        assert (pd == rec["p_d_log"] == -np.inf) or abs(pd - rec["p_d_log"]) <= 1e-6, (rec["n"], pd, rec["p_d_log"])
         states, logp = beam.export(M, inst.n_spins)
         S = states.cpu().numpy()
         got_X = P.cluster_of_states(np.where(S == 0, -1, S))[:, : rec["n"] + 1]
@@ -68,7 +70,8 @@ def test_stepwise_beam_zephyr_t4_planted(chi):
     for rec in ref["steps"]:
         p = beam.marginals().cpu().numpy()
         assert np.abs(p - rec["p"]).max() <= 1e-8
-        beam.step()
+        pd = beam.step()
+        assert (pd == rec["p_d_log"] == -np.inf) or abs(pd - rec["p_d_log"]) <= 1e-9, (rec["n"], pd, rec["p_d_log"])
         states, logp = beam.export(16, inst.n_spins)
         S = states.cpu().numpy()
         got_X = P.cluster_of_states(np.where(S == 0, -1, S))[:, : rec["n"] + 1]
