@@ -1023,6 +1023,75 @@ static RowGeom::Med mirror_med(const RowGeom::Med& m) {
   return r;
 }
 
+// ---- the plain accumulations as batched GEMMs ------------------------------
+// Where the item index of an accumulation splits into two disjoint bit sets,
+// its sum is a dense product over those sets:
+//   G2:  l = (l_d, b') and hL (the horizontal bits of l outside b') lies in l_d:
+//        G2[l_d][rd] = sum_{b', b} K[l(l_d, b')][b][:]^T W2[rd][b'][hL(l_d)][b][:],
+//        one GEMM per hL value over rows (the other l_d bits, g), columns (rd, j)
+//        and reduction (b', b);
+//   out: rho = (rd, a') and hR lies in a':
+//        out[rho] = sum_{b', b} A[a' + da' b'][:][b] Y2[rd][b'][hR(a')][b][:],
+//        one GEMM per hR value over rows (the other a' bits, a), columns (rd, j).
+// The operands are gathered into layouts where those indices are strided
+// (Kp [hL][ld_rest][b'][b][g], Ap [hR][a'_rest][b'][a][b]), the GEMM writes
+// [h][rest][rd][row][j], and a scatter restores the diagram's layout.
+struct Split {
+  uint32_t in_sub = 0;   // positions, within the outer index, of the batch bits
+  uint32_t rest = 0;     // the other bits of the outer index
+  int nh = 1, nrest = 1;
+};
+
+// Kp[hL][ldr][b'] = K[l] (blocks of blk doubles), l = pdep(ld, pos_d_ell) | pdep(b', pos_b2)
+__global__ void gather_conn_kernel(const double* __restrict__ K, int64_t nl, uint32_t pos_ld, uint32_t pos_b2,
+                                   Split sp, int db2, int blk, double* __restrict__ Kp) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= nl * blk) return;
+  const uint32_t l = uint32_t(idx / blk);
+  const int e = int(idx % blk);
+  const uint32_t ld = pext_dev(l, pos_ld), b2 = pext_dev(l, pos_b2);
+  const uint32_t h = pext_dev(ld, sp.in_sub), r = pext_dev(ld, sp.rest);
+  Kp[((int64_t(h) * sp.nrest + r) * db2 + b2) * blk + e] = K[idx];
+}
+
+// Ap[hR][ar][b'] = A[a' + da2 b'] (blocks of blk doubles)
+__global__ void gather_site_kernel(const double* __restrict__ A, int da2, int db2, Split sp, int blk,
+                                   double* __restrict__ Ap) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(da2) * db2 * blk) return;
+  const uint32_t sg = uint32_t(idx / blk);
+  const int e = int(idx % blk);
+  const uint32_t a2 = sg % uint32_t(da2), b2 = sg / uint32_t(da2);
+  const uint32_t h = pext_dev(a2, sp.in_sub), r = pext_dev(a2, sp.rest);
+  Ap[((int64_t(h) * sp.nrest + r) * db2 + b2) * blk + e] = A[idx];
+}
+
+// out[outer(h, r, rd)] = Cp[h][r][rd] (blocks of blk doubles); the outer
+// index is pdep(rd, pos_rd) | pdep(inner, pos_inner), inner = pdep(h) | pdep(r)
+__global__ void scatter_out_kernel(const double* __restrict__ Cp, Split sp, int nrd, uint32_t pos_rd,
+                                   uint32_t pos_inner, int blk, double* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t total = int64_t(sp.nh) * sp.nrest * nrd * blk;
+  if (idx >= total) return;
+  const int e = int(idx % blk);
+  int64_t q = idx / blk;
+  const uint32_t rd = uint32_t(q % nrd);
+  q /= nrd;
+  const uint32_t r = uint32_t(q % sp.nrest), h = uint32_t(q / sp.nrest);
+  const uint32_t inner = pdep_dev(h, sp.in_sub) | pdep_dev(r, sp.rest);
+  const uint32_t o = pdep_dev(rd, pos_rd) | pdep_dev(inner, pos_inner);
+  out[int64_t(o) * blk + e] = Cp[idx];
+}
+
+static Split make_split(uint32_t batch_bits_in_outer, int n_outer) {
+  Split sp;
+  sp.in_sub = batch_bits_in_outer;
+  sp.rest = uint32_t(n_outer - 1) & ~batch_bits_in_outer;
+  sp.nh = 1 << popcount32(sp.in_sub);
+  sp.nrest = 1 << popcount32(sp.rest);
+  return sp;
+}
+
 // -------------------------------------------------------------- the zipper
 struct Zipper {
   const tnb_clusters* cl;
@@ -1195,6 +1264,74 @@ struct Zipper {
     }
   }
 
+  // ---- G2 and out as batched GEMMs (FP64; see gather_conn_kernel) ----------
+  static bool g2_gemm_ok(const RowGeom::Med& md, const MedF& f) {
+    const uint32_t all = uint32_t(md.dL - 1);
+    return (md.pos_d_ell & md.pos_b2) == 0 && (md.pos_d_ell | md.pos_b2) == all && (f.hL_pos & ~md.pos_d_ell) == 0 &&
+           md.dL >= 4096;
+  }
+  static bool out_gemm_ok(const RowGeom::Med& md, const MedF& f) {
+    const uint32_t all = uint32_t(md.dR - 1);
+    return (md.pos_d_rho & md.pos_a2) == 0 && (md.pos_d_rho | md.pos_a2) == all && (f.hR_pos & ~md.pos_a2) == 0 &&
+           md.dR >= 4096;
+  }
+  // G2[ld][rd] (Dg x s) from the connector K [l][b][g] and W2 [rd][b'][hL][b][s]
+  void g2_gemm(const RowGeom::Med& md, const MedF& f, const double* Kc, const double* W2, int Dg, int Db, int s,
+               double* G2) {
+    const Split sp = make_split(pext_host(f.hL_pos, md.pos_d_ell), md.dld);
+    const int blk = Db * Dg;
+    const int64_t nK = int64_t(md.dL) * blk, nC = int64_t(md.dld) * md.drd * Dg * s;
+    double* Kp = tb<double>(cK, size_t(nK));
+    double* Cp = tb<double>(cO, size_t(nC));
+    {
+      KTimer _t("medf_perm", st, 0.0, 16.0 * double(nK));
+      hipLaunchKernelGGL(gather_conn_kernel, dim3(blocks(nK)), dim3(256), 0, st, Kc, int64_t(md.dL), md.pos_d_ell,
+                         md.pos_b2, sp, md.db2, blk, Kp);
+    }
+    const int M = sp.nrest * Dg, N = md.drd * s, Kd = md.db2 * Db;
+    la::Operand a{Kp, int64_t(sp.nrest) * md.db2 * blk, la::Ix{uint32_t(Dg), int64_t(md.db2) * blk, 1},
+                  la::Ix{uint32_t(Db), int64_t(blk), Dg}};
+    la::Operand b{W2, int64_t(Db) * s, la::Ix{uint32_t(Db), int64_t(f.nHL) * Db * s, s},
+                  la::Ix{uint32_t(s), int64_t(md.db2) * f.nHL * Db * s, 1}};
+    la::gemm_mfma(sp.nh, M, N, Kd, a, b, Cp, la::Ix{uint32_t(Dg), int64_t(md.drd) * Dg * s, s},
+                  la::Ix{uint32_t(s), int64_t(Dg) * s, 1}, int64_t(sp.nrest) * md.drd * Dg * s, 1.0, 0.0, st,
+                  "medf_G2");
+    {
+      KTimer _t("medf_perm", st, 0.0, 16.0 * double(nC));
+      hipLaunchKernelGGL(scatter_out_kernel, dim3(blocks(nC)), dim3(256), 0, st, Cp, sp, 1, 0u,
+                         uint32_t(md.dld - 1), md.drd * Dg * s, G2);
+    }
+    HIPC(hipGetLastError());
+  }
+  // out[rho] (Da x s) from the site A [a' + da2 b'][a][b] and Y2 [rd][b'][hR][b][s]
+  void out_gemm(const RowGeom::Med& md, const MedF& f, const Site& A, const double* Y2, int Da, int Db, int s,
+                double* out) {
+    const Split sp = make_split(pext_host(f.hR_pos, md.pos_a2), md.da2);
+    const int blk = Da * Db;
+    const int64_t nA = int64_t(A.size()), nC = int64_t(md.dR) * Da * s;
+    double* Ap = tb<double>(cA, size_t(nA));
+    double* Cp = tb<double>(cO, size_t(nC));
+    {
+      KTimer _t("medf_perm", st, 0.0, 16.0 * double(nA));
+      hipLaunchKernelGGL(gather_site_kernel, dim3(blocks(nA)), dim3(256), 0, st, A.data.p, md.da2, md.db2, sp, blk,
+                         Ap);
+    }
+    const int M = sp.nrest * Da, N = md.drd * s, Kd = md.db2 * Db;
+    la::Operand a{Ap, int64_t(sp.nrest) * md.db2 * blk, la::Ix{uint32_t(Da), int64_t(md.db2) * blk, Db},
+                  la::Ix{uint32_t(Db), int64_t(blk), 1}};
+    la::Operand b{Y2, int64_t(Db) * s, la::Ix{uint32_t(Db), int64_t(f.nHR) * Db * s, s},
+                  la::Ix{uint32_t(s), int64_t(md.db2) * f.nHR * Db * s, 1}};
+    la::gemm_mfma(sp.nh, M, N, Kd, a, b, Cp, la::Ix{uint32_t(Da), int64_t(md.drd) * Da * s, s},
+                  la::Ix{uint32_t(s), int64_t(Da) * s, 1}, int64_t(sp.nrest) * md.drd * Da * s, 1.0, 0.0, st,
+                  "medf_out");
+    {
+      KTimer _t("medf_perm", st, 0.0, 16.0 * double(nC));
+      hipLaunchKernelGGL(scatter_out_kernel, dim3(blocks(nC)), dim3(256), 0, st, Cp, sp, md.drd, md.pos_d_rho,
+                         md.pos_a2, Da * s, out);
+    }
+    HIPC(hipGetLastError());
+  }
+
   // D X for site k of row geometry g; X: (ds*Dg) x s, out: (dm*Da) x s
   void apply_block(const RowGeom& g, int k, const Site& A, const double* Kc, int Dg, int dm, const double* X, int s,
                    double* out) {
@@ -1274,7 +1411,9 @@ struct Zipper {
         HIPC(hipGetLastError());
       }
       T* oT = out_T<T>(out, int64_t(md.dR) * Da * s, cO);
-      {
+      if (sizeof(T) == sizeof(double) && out_gemm_ok(md, f)) {
+        out_gemm(md, f, A, reinterpret_cast<const double*>(YfT), Da, Db, s, out);
+      } else {
         KTimer _t2(TNB_TN("medf_out"), st, double(md.dR) * md.db2 * 2.0 * Da * Db * s,
                    sz * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
                          double(md.dR) * Da * s));
@@ -1359,7 +1498,9 @@ struct Zipper {
         HIPC(hipGetLastError());
       }
       T* G2T = out_T<T>(G2, int64_t(md.dld) * md.drd * Dg * s, cO);
-      {
+      if (sizeof(T) == sizeof(double) && g2_gemm_ok(md, f)) {
+        g2_gemm(md, f, Kc, reinterpret_cast<const double*>(YfT), Dg, Db, s, G2);
+      } else {
         KTimer _t2(TNB_TN("medf_G2"), st, double(md.dL) * md.drd * 2.0 * Db * Dg * s,
                    sz * (double(md.dL) * Db * Dg + double(md.drd) * md.db2 * f.nHL * Db * s +
                          double(md.dld) * md.drd * Dg * s));
