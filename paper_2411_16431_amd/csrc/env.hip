@@ -740,22 +740,25 @@ __global__ void __launch_bounds__(256) medf_acc_pipe(MedF f, const T* __restrict
 // without any data movement.
 //   apply : out[l] (Da x s)  = sum_{x in l} w(x) A[v'(x)] . (K[rho(x)] . Xt[u(x)])
 //   applyT: G[u]  (Dg x s)   = sum_{x in u} w(x) K[rho(x)]^T . (A[v'(x)]^T . Y[l(x)])
-// One wave per output block for apply (its x range is short); four waves
-// splitting the x range of an output block for applyT, summed through LDS.
-// apply is capped at five waves per SIMD; NJ <= 3 fits that without spilling.
+// apply: one wave per output block when its x range is short, else four
+// waves splitting it; applyT: four waves splitting the x range of an output
+// block; partial tiles are summed through LDS.  apply is capped at five waves
+// per SIMD; NJ <= 3 fits that without spilling.
 template <int NJ, int VIEW = 0, class T = double>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) site_apply_mfma(uint32_t PL, uint32_t FREE, int nfree, uint32_t PR,
                                                       uint32_t Bup, uint32_t Bdn, const T* __restrict__ w,
                                                       const T* __restrict__ A, int Da, int Db,
                                                       const T* __restrict__ Kc, int Dg,
                                                       const T* __restrict__ Xt, int s,
                                                       T* __restrict__ out) {
-  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  // one to four waves per output block; wave wv takes x = wv, wv + nw, ...
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const uint32_t l = blockIdx.x;
   typename MF<T>::v4 acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::zero();
-  for (int f = 0; f < nfree; ++f) {
+  for (int f = wv; f < nfree; f += nw) {
     const uint32_t x = pdep_dev(l, PL) | pdep_dev(uint32_t(f), FREE);
     const T wx = w[x];
     if (wx == 0.0) continue;
@@ -785,13 +788,30 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) si
     }
   }
   T* o = out + size_t(l) * Da * s;
+  if (nw == 1) {  // uniform over the workgroup
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = MF<T>::row(v, lk), jj = 16 * j + li;
+        if (a < Da && jj < s) o[size_t(a) * s + jj] = acc[j][v];
+      }
+    return;
+  }
+  __shared__ T red[4][16][16 * NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = MF<T>::row(v, lk), jj = 16 * j + li;
-      if (a < Da && jj < s) o[size_t(a) * s + jj] = acc[j][v];
+    for (int v = 0; v < 4; ++v) red[wv][MF<T>::row(v, lk)][16 * j + li] = acc[j][v];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 16 * 16 * NJ; i += blockDim.x) {
+    const int a = i / (16 * NJ), jj = i % (16 * NJ);
+    if (a < Da && jj < s) {
+      T sum = red[0][a][jj];
+      for (int q = 1; q < nw; ++q) sum += red[q][a][jj];
+      o[size_t(a) * s + jj] = sum;
     }
+  }
 }
 
 template <int NJ, class T = double>
@@ -1193,11 +1213,13 @@ struct Zipper {
   void launch_site_apply(int s, unsigned grid, uint32_t PL, uint32_t FREE, int nfree, uint32_t PR, uint32_t Bup,
                          uint32_t Bdn, const T* w, const T* A, int Da, int Db, const T* Kc, int Dg, const T* Xt,
                          T* out) {
+    // four waves split the x values of a block once there are enough of them
+    const unsigned threads = nfree >= 8 ? 256u : 64u;
     switch ((s + 15) / 16) {
 #define TNB_SITE_CASE(NJV)                                                                                  \
   case NJV:                                                                                                 \
-    hipLaunchKernelGGL((site_apply_mfma<NJV, VIEW, T>), dim3(grid), dim3(64), 0, st, PL, FREE, nfree, PR,  \
-                       Bup, Bdn, w, A, Da, Db, Kc, Dg, Xt, s, out);                                          \
+    hipLaunchKernelGGL((site_apply_mfma<NJV, VIEW, T>), dim3(grid), dim3(threads), 0, st, PL, FREE, nfree, \
+                       PR, Bup, Bdn, w, A, Da, Db, Kc, Dg, Xt, s, out);                                      \
     break;
       TNB_SITE_CASE(1)
       TNB_SITE_CASE(2)

@@ -561,12 +561,16 @@ static void tall_svd(const double* M, int64_t n, int m, double* Uo, double* S, d
   HIPC(hipGetLastError());
   // Q (into Uo) = Q1 W
   gemm(1, int(n), m, m, View{Q1, m, 1, 0}, View{W, m, 1, 0}, Uo, m, 0, 1.0, 0.0, ws, st);
-  // R = Q^T M  (m x m) into G
-  gemm(1, m, m, n, View{Uo, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
-  double* UR = W;  // reuse
-  hestenes(G, m, UR, Vo, S, st);
-  // Uo <- Q U_R  (through Q1 as scratch)
-  gemm(1, int(n), m, m, View{Uo, m, 1, 0}, View{UR, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
+  // R^T = M^T Q (m x m) into G.  R = Q^T M has nearly orthogonal rows (Q
+  // comes from the eigenvectors of M^T M), so the one-sided Jacobi SVD of
+  // R^T = U' S V'^T converges in a sweep or two; then R = V' S U'^T.
+  gemm(1, m, m, n, View{M, 1, m, 0}, View{Uo, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  double* Up = W;                      // U' (right singular vectors of R)
+  double* Vp = V;                      // V' (left ones); V is free once W2 is formed
+  hestenes(G, m, Up, Vp, S, st);
+  HIPC(hipMemcpyAsync(Vo, Up, size_t(m) * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // Uo <- Q V'  (through Q1 as scratch)
+  gemm(1, int(n), m, m, View{Uo, m, 1, 0}, View{Vp, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
   HIPC(hipMemcpyAsync(Uo, Q1, size_t(n) * m * sizeof(double), hipMemcpyDeviceToDevice, st));
 }
 
