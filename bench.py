@@ -49,8 +49,8 @@ def peak_of(name):
 def unit_class(name):
     return "mfma" if name.replace("_f32", "") in MFMA_KERNELS else "alu"
 # library timer -> the kernel instance rocprofv3 reports for it
-ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0>", "medf_W2": "medf_bin_pipe<1, 1, 0>",
-                "medf_lbin": "medf_bin_pipe<0, 1, 1>"}
+ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0, double>", "medf_W2": "medf_bin_pipe<1, 1, 0, double>",
+                "medf_lbin": "medf_bin_pipe<0, 1, 1, double>"}
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
@@ -126,7 +126,7 @@ def write_traffic(fetch_csv, write_csv, timer, workload, copy_bytes=8 << 27):
         out["source_sha256"] = hashlib.sha256(fh.read()).hexdigest()
     out["commands"] = [
         "rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_%s -o %s -- python3 bench.py --steps 1 "
-        "--warmup 0 --no-cpu-baseline --no-planted --copy-calibration" % (c, c.split("_")[0].lower(),
+        "--warmup 0 --no-cpu-baseline --no-planted --no-f32 --copy-calibration" % (c, c.split("_")[0].lower(),
                                                                           c.split("_")[0].lower())
         for c in ("FETCH_SIZE", "WRITE_SIZE")]
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (timer, workload))

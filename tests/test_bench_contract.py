@@ -39,7 +39,7 @@ def test_write_traffic_scales_by_the_copy_dispatch(tmp_path, monkeypatch):
     import bench
     hdr = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
     kib = 1 << 20
-    name = "void tnb::medf_bin_pipe<0, 1, 0>(tnb::MedF, double const*)"
+    name = "void tnb::medf_bin_pipe<0, 1, 0, double>(tnb::MedF, double const*)"
     fetch = hdr + "".join("%d,%s,FETCH_SIZE,%r\n" % (d, '"%s"' % name, 1.5 * kib) for d in (1, 2)) \
         + "3,__amd_rocclr_copyBuffer,FETCH_SIZE,%r\n" % (0.5 * kib)
     write = hdr + "".join("%d,%s,WRITE_SIZE,%r\n" % (d, '"%s"' % name, 1.0 * kib) for d in (1, 2)) \
