@@ -56,6 +56,7 @@ ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0, double>", "medf_W2": "medf_bi
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
 # Valid only for the kernel source they were taken on (hash of its file).
 KERNEL_SRC = os.path.join(ROOT, "paper_2411_16431_amd", "csrc", "env.hip")
+TUNING_FILE = os.path.join(ROOT, "paper_2411_16431_amd", "tuning_mi355x.json")
 
 
 def measured_traffic(kernel, workload):
@@ -148,6 +149,10 @@ def parse():
                     help="skip the planted-instance energy gap (profiling runs: keeps rocprof's kernel averages to the timed workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 1 GiB device copy, the reference dispatch for HBM byte counters")
+    ap.add_argument("--autotune", metavar="JSON",
+                    help="measure the launch variants of every new shape during warm-up and write the table here")
+    ap.add_argument("--tuning", default=TUNING_FILE,
+                    help="launch-variant table used when not measuring (default: the committed MI355X table)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: turn two rocprofv3 counter files of the dominant kernel into profiles/*_traffic.json")
     ap.add_argument("--traffic-kernel", default="medf_Y2")
@@ -317,6 +322,10 @@ def main():
     wl = WORKLOADS[args.workload]
     inst, E0 = make(wl)
     env_kw = dict(power_iters=args.power_iters, seed=4242)
+    if args.autotune:
+        pk.autotune(True, args.autotune)
+    elif args.tuning and os.path.exists(args.tuning):
+        pk.autotune(False, args.tuning)
 
     def one():
         return pk.solve(inst, wl["beta"], chi=wl["chi"], M=wl["M"], K=wl["K"], **env_kw)
@@ -325,6 +334,8 @@ def main():
         one()
         print("warmup %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    if args.autotune:
+        pk.autotune(False, args.autotune)  # timed steps use the measured table
     pk.profile_enable(True)
     t0 = time.perf_counter()
     res = None
@@ -387,6 +398,7 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "adjoint": adj, "fp32": f32,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
         "kernels": kernel_table(prof, args.steps),
+        "tuning": args.autotune or (args.tuning if args.tuning and os.path.exists(args.tuning) else None),
     }
     print(json.dumps(out), flush=True)
     if args.copy_calibration:

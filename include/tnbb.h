@@ -280,6 +280,18 @@ tnb_status tnb_row_moments(tnb_beam* beam, double* d_m1, int64_t m1_len, double*
  * capacity rule as tnb_row_moments (no couplings). */
 tnb_status tnb_row_moments_per_branch(tnb_beam* beam, double* d_m1, int64_t m1_len, tnb_stream stream);
 
+/* Autotuner of kernel launch variants.  Some diagram stages have several
+ * launch variants that give bit-identical results and differ only in how the
+ * work is tiled over workgroups (e.g. sketch columns per workgroup of the
+ * binned mediating kernel).  mode 1: the first launch of every new shape
+ * times each candidate once with HIP events on the launch stream and keeps
+ * the fastest; mode 0: use the stored choices and the default variant for
+ * unseen shapes.  path (may be NULL: in memory only) names a JSON file of
+ * {"shape": variant} that is read now and rewritten after every new choice.
+ * Process-wide; calls that tune concurrently are serialised.
+ * Errors: TNB_EINVAL (mode). */
+tnb_status tnb_autotune(int32_t mode, const char* path);
+
 /* Measurement support.  tnb_profile_enable(1) clears and starts recording a
  * pair of HIP events around every launch of the instrumented kernels, on the
  * stream the kernel runs on, together with its algorithmic flop and byte

@@ -46,6 +46,7 @@ SIGNATURES = {
     "tnb_row_layout": (c_int32, [c_void_p, P(c_int32), P(c_int32), c_void_p, c_void_p, c_int32]),
     "tnb_row_moments": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
     "tnb_row_moments_per_branch": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "tnb_autotune": (c_int32, [c_int32, ctypes.c_char_p]),
     "tnb_profile_enable": (c_int32, [c_int32]),
     "tnb_profile_query": (c_int32, [ctypes.c_char_p, P(c_double), P(c_int64), P(c_double), P(c_double)]),
     "tnb_profile_names": (c_int32, [ctypes.c_char_p, c_int64]),

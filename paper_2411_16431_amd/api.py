@@ -293,6 +293,12 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
                 beam=beam, spin_marginals=marg)
 
 
+def autotune(measure, path=None):
+    """tnb_autotune: measure (True) or reuse (False) the fastest launch
+    variant per shape; path: JSON cache of the choices."""
+    _check(L.lib().tnb_autotune(1 if measure else 0, path.encode() if path else None))
+
+
 def select_lowest(states, E, K):
     """tnb_select_lowest on cuda tensors: the K lowest distinct of the given
     configurations (int8 [n, N]) and energies ([n]), by energy then spin vector."""

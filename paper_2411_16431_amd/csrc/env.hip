@@ -15,7 +15,10 @@
 // Each output block is owned by one workgroup (no atomics: deterministic).
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <string>
 
 #include "env.h"
 
@@ -447,13 +450,9 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const T* __restrict
 // has consumed its registers, overlapping stage 2 and the barriers.  Both
 // modes read P as [item][k][b] (16 consecutive b per load): MODE 1 gets the
 // MPS site as stored, MODE 0 a transposed copy of the connector, [l][g][b].
-// The register budget is capped at four waves per SIMD (128 registers, a few
-// spilled outside the item loop): the extra wave hides more load latency than
-// the spills cost.
-template <int MODE, int NJ, int VIEW = 0, class T = double>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const T* __restrict__ P,
-                                                     const T* __restrict__ Q, int Da, int Db, int Kd, int s,
-                                                     T* __restrict__ out) {
+template <int MODE, int NJ, class T>
+__device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict__ P, const T* __restrict__ Q, int Da,
+                                              int Db, int Kd, int s, T* __restrict__ out) {
   constexpr int KK = 8, QS = 16 * NJ;  // reduction <= 4 * KK
   __shared__ T Ts[4][16][QS];
   __shared__ T Ws[4][16];
@@ -593,6 +592,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
       }
     }
   }
+}
+
+// The binned stage with one 16-column sketch tile per workgroup, capped at
+// four waves per SIMD (128 registers, a few spilled outside the item loop): the
+// extra wave hides more load latency than the spills cost.
+template <int MODE, int NJ, int VIEW = 0, class T = double>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const T* __restrict__ P,
+                                                     const T* __restrict__ Q, int Da, int Db, int Kd, int s,
+                                                     T* __restrict__ out) {
+  medf_bin_body<MODE, NJ, T>(f, P, Q, Da, Db, Kd, s, out);
+}
+
+// The same body with NJ column tiles per workgroup and no register cap: each
+// P tile serves NJ tiles of the sketch at fewer waves per SIMD.  Which of the
+// two is faster depends on the shape; the autotuner decides.
+template <int MODE, int NJ, int VIEW = 0, class T = double>
+__global__ void __launch_bounds__(256) medf_bin_wide(MedF f, const T* __restrict__ P, const T* __restrict__ Q, int Da,
+                                                     int Db, int Kd, int s, T* __restrict__ out) {
+  medf_bin_body<MODE, NJ, T>(f, P, Q, Da, Db, Kd, s, out);
 }
 
 // medf_acc_mfma with the next item's operands prefetched into registers
@@ -1043,6 +1061,82 @@ static RowGeom::Med mirror_med(const RowGeom::Med& m) {
   return r;
 }
 
+// ---- kernel-variant autotuner ------------------------------------------------
+// Several launch variants compute the same result bit for bit (they differ in
+// how the work is tiled over workgroups).  For each launch shape the tuner
+// either returns the cached choice, or (when measuring) times every candidate
+// once with HIP events on the launch stream, keeps the fastest, and writes the
+// table to its JSON file.  Unseen shapes get variant 0 when not measuring.
+struct Tuner {
+  std::mutex mu;
+  int measure = 0;
+  std::string path;
+  std::map<std::string, int> choice;
+
+  void load() {
+    choice.clear();
+    if (path.empty()) return;
+    FILE* fh = std::fopen(path.c_str(), "r");
+    if (!fh) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, fh)) {
+      char key[400];
+      int v = 0;
+      if (std::sscanf(line, " \"%399[^\"]\" : %d", key, &v) == 2) choice[key] = v;
+    }
+    std::fclose(fh);
+  }
+  void save() {
+    if (path.empty()) return;
+    FILE* fh = std::fopen(path.c_str(), "w");
+    if (!fh) return;
+    std::fprintf(fh, "{\n");
+    size_t i = 0;
+    for (auto& kv : choice) std::fprintf(fh, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < choice.size() ? "," : "");
+    std::fprintf(fh, "}\n");
+    std::fclose(fh);
+  }
+  template <class Run>
+  int pick(const std::string& key, int n, Run run, hipStream_t st) {
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      auto it = choice.find(key);
+      if (it != choice.end() && it->second < n) {
+        run(it->second);
+        return it->second;
+      }
+      if (!measure || n <= 1) {
+        run(0);
+        return 0;
+      }
+    }
+    std::vector<float> ms(n, 0.f);
+    hipEvent_t a, b;
+    HIPC(hipEventCreate(&a));
+    HIPC(hipEventCreate(&b));
+    for (int v = 0; v < n; ++v) {
+      HIPC(hipEventRecord(a, st));
+      run(v);
+      HIPC(hipEventRecord(b, st));
+      HIPC(hipEventSynchronize(b));
+      HIPC(hipEventElapsedTime(&ms[v], a, b));
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    int best = 0;
+    for (int v = 1; v < n; ++v)
+      if (ms[v] < ms[best]) best = v;
+    std::lock_guard<std::mutex> lock(mu);
+    choice[key] = best;
+    save();
+    return best;
+  }
+};
+Tuner& tuner() {
+  static Tuner t;
+  return t;
+}
+
 // ---- the plain accumulations as batched GEMMs ------------------------------
 // Where the item index of an accumulation splits into two disjoint bit sets,
 // its sum is a dense product over those sets:
@@ -1247,6 +1341,30 @@ struct Zipper {
       default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
     }
   }
+  // The binned stage (Kd <= 32): variant 0 is medf_bin_pipe with one 16-column
+  // tile per workgroup, variants 1 and 2 medf_bin_wide with 2 and 3 tiles.
+  template <int MODE, int VIEW, class T>
+  void launch_bin(const MedF& f, unsigned G, int rows, const T* P, const T* Q, int Da, int Db, int Kd, int s,
+                  T* out) {
+    auto run = [&](int v) {
+      const int njv = v + 1;
+      const unsigned njt = unsigned((s + 16 * njv - 1) / (16 * njv));
+      const dim3 grid((G + 7) / 8 * 8 * njt, unsigned((rows + 15) / 16));
+      if (v == 0)
+        hipLaunchKernelGGL((medf_bin_pipe<MODE, 1, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
+      else if (v == 1)
+        hipLaunchKernelGGL((medf_bin_wide<MODE, 2, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
+      else
+        hipLaunchKernelGGL((medf_bin_wide<MODE, 3, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
+      HIPC(hipGetLastError());
+    };
+    const int n = std::min(3, (s + 15) / 16);
+    char key[160];
+    std::snprintf(key, sizeof key, "bin m%d v%d f%d Kd%d s%d rows%d G%u dL%d dR%d", MODE, VIEW, int(sizeof(T)), Kd, s,
+                  rows, G, f.md.dL, f.md.dR);
+    tuner().pick(key, n, run, st);
+  }
+
   // medf_acc_pipe / medf_acc_mfma for NJ = ceil(s / 16)
   template <int MODE, int VIEW, class T>
   void launch_acc(bool pipe, int nj, dim3 grid, const MedF& f, const T* P, const T* Q, int rows, int Db, int s,
@@ -1420,9 +1538,7 @@ struct Zipper {
           // within the kernel's four-waves-per-SIMD cap; the kernel reads the
           // connector as [l][g][b] (contiguous along b)
           const T* cT = transposed<T>(Kc, int64_t(md.dL), Db, Dg, connT);
-          const unsigned G = unsigned(md.drd * md.db2 * f.chR);
-          hipLaunchKernelGGL((medf_bin_pipe<0, 1, 0, T>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0,
-                             st, f, cT, X2T, Da, Db, Dg, s, YfT);
+          launch_bin<0, 0, T>(f, unsigned(md.drd * md.db2 * f.chR), Db, cT, X2T, Da, Db, Dg, s, YfT);
         } else {
           const size_t shm = medf_bin_lds(Dg, nj) * sizeof(T) / sizeof(double);
           check_lds(shm);
@@ -1508,9 +1624,7 @@ struct Zipper {
                    sz * (double(md.da2) * md.db2 * Da * Db + double(md.dR) * Da * s +
                          double(md.drd) * md.db2 * f.nHL * Db * s));
         if (Da <= 32) {
-          const unsigned G = unsigned(md.drd * md.db2 * f.chL);
-          hipLaunchKernelGGL((medf_bin_pipe<1, 1, 0, T>), dim3((G + 7) / 8 * 8 * nj, (Db + 15) / 16), dim3(256), 0,
-                             st, f, AT_, YT, Da, Db, Da, s, YfT);
+          launch_bin<1, 0, T>(f, unsigned(md.drd * md.db2 * f.chL), Db, AT_, YT, Da, Db, Da, s, YfT);
         } else {
           const size_t shm = medf_bin_lds(Da, nj) * sizeof(T) / sizeof(double);
           check_lds(shm);
@@ -1680,9 +1794,7 @@ struct Zipper {
                          double(mm.drd) * mm.db2 * f.nHR * Da * s));
         if (t <= 32) {
           const T* LTT = in_T<T>(LT.p, int64_t(mm.dL) * Da * t, cK);
-          const unsigned G = unsigned(mm.drd * mm.db2 * f.chR);
-          hipLaunchKernelGGL((medf_bin_pipe<0, 1, 1, T>), dim3((G + 7) / 8 * 8 * nj, (Da + 15) / 16), dim3(256), 0,
-                             st, f, LTT, QT, Db, Da, t, s, YfT);
+          launch_bin<0, 1, T>(f, unsigned(mm.drd * mm.db2 * f.chR), Da, LTT, QT, Db, Da, t, s, YfT);
         } else {
           const size_t shm = medf_bin_lds(t, nj) * sizeof(T) / sizeof(double);
           check_lds(shm);
@@ -2174,5 +2286,16 @@ extern "C" tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32
     }
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(st));  // the scratch is freed on return
+  });
+}
+
+extern "C" tnb_status tnb_autotune(int32_t mode, const char* path) {
+  return guarded([&] {
+    if (mode != 0 && mode != 1) fail(TNB_EINVAL, "mode must be 0 (use the table) or 1 (measure unseen shapes)");
+    Tuner& t = tuner();
+    std::lock_guard<std::mutex> lock(t.mu);
+    t.measure = mode;
+    t.path = path ? path : "";
+    t.load();
   });
 }

@@ -63,7 +63,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) g
                                                          const double* __restrict__ A, int64_t ars, int64_t acs,
                                                          int64_t abs_, const double* __restrict__ B, int64_t brs,
                                                          int64_t bcs, int64_t bbs, double* __restrict__ P,
-                                                         int64_t pbs_chunk, int64_t pbs_batch, int nb) {
+                                                         int64_t pbs_chunk, int64_t pbs_batch, int nb,
+                                                         double* __restrict__ C, int64_t ldc, int64_t bsc,
+                                                         double alpha, double beta) {
   __shared__ double red[64][65];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const int b = int(blockIdx.y) % nb, chunk = int(blockIdx.y) / nb;
@@ -112,6 +114,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) g
     }
     __syncthreads();
   }
+  if (C) {  // a single K chunk: the result goes straight to C
+    for (int i = threadIdx.x; i < M * N; i += blockDim.x) {
+      double* dst = C + b * bsc + int64_t(i / N) * ldc + i % N;
+      const double v = red[i / N][i % N];
+      *dst = beta == 0.0 ? alpha * v : alpha * v + beta * *dst;
+    }
+    return;
+  }
   double* Pb = P + chunk * pbs_chunk + b * pbs_batch;
   for (int i = threadIdx.x; i < M * N; i += blockDim.x) Pb[i] = red[i / N][i % N];
 }
@@ -136,8 +146,14 @@ static void gemm_part(int batch, int M, int N, int64_t K, View A, View B, double
   KTimer _t("gemm", s, 2.0 * M * double(N) * double(K) * batch,
             8.0 * (double(M) * K + double(K) * N + double(M) * N) * batch);
   if (M <= 64 && N <= 64) {
+    const bool direct = nchunk == 1;
     hipLaunchKernelGGL(gemm_small_kernel, dim3(1, unsigned(batch * nchunk)), dim3(256), 0, s, M, N, K, kchunk, A.p,
-                       A.rs, A.cs, A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
+                       A.rs, A.cs, A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch, direct ? C : nullptr, ldc,
+                       bsc, alpha, beta);
+    if (direct) {
+      HIPC(hipGetLastError());
+      return;
+    }
   } else {
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(TILE, TILE), 0, s, M, N, K, kchunk, A.p, A.rs, A.cs,
                        A.bs, B.p, B.rs, B.cs, B.bs, P, per * batch, per, batch);
@@ -353,13 +369,13 @@ __global__ void inv_sqrt_weights_kernel(const double* __restrict__ V, const doub
 }
 
 // One-sided Jacobi SVD (Hestenes; Golub & Van Loan Sec. 8.6.3) of a small
-// m x m matrix A (row-major, overwritten by U*S): rotations orthogonalise the
-// columns pairwise, round-robin over disjoint pairs.  Singular values are
-// accurate to eps * sigma_max.  Outputs sorted descending: S[m], U (m x m,
-// columns of A normalised; zero for sigma = 0), V (m x m).
-// A and V are the working matrices (global memory, or LDS in the _lds
-// variant); sh is 2560 doubles of LDS scratch.
-__device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict__ U, double* __restrict__ V,
+// n x m matrix A (row-major, overwritten by U*S; room for max(n, m) rows):
+// rotations orthogonalise the columns pairwise, round-robin over disjoint
+// pairs.  Singular values are accurate to eps * sigma_max.  Outputs sorted
+// descending: S[m], U (n x m, columns of A normalised; zero for sigma = 0),
+// V (m x m).  A and V are the working matrices (global memory, or LDS in the
+// _lds variants); sh is 2560 doubles of LDS scratch.
+__device__ void hestenes_body(double* __restrict__ A, int n, int m, double* __restrict__ U, double* __restrict__ V,
                               double* __restrict__ S, double* __restrict__ sh) {
   double* cs = sh;           // [512]
   double* sn = sh + 512;     // [512]
@@ -388,7 +404,7 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
         }
         double al = 0.0, be = 0.0, ga = 0.0;
         if (act && q < m)
-          for (int i = sub; i < m; i += 16) {
+          for (int i = sub; i < n; i += 16) {
             const double x = A[i * m + p], y = A[i * m + q];
             al = fma(x, x, al);
             be = fma(y, y, be);
@@ -416,16 +432,21 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
         }
       }
       __syncthreads();
-      for (int idx = tid; idx < (mm / 2) * m; idx += nt) {
-        const int a = idx / m, i = idx % m;
+      const int nr = n > m ? n : m;
+      for (int idx = tid; idx < (mm / 2) * nr; idx += nt) {
+        const int a = idx / nr, i = idx % nr;
         const int p = pp[a], q = qq[a];
         if (q >= m || sn[a] == 0.0) continue;
-        const double x = A[i * m + p], y = A[i * m + q];
-        A[i * m + p] = cs[a] * x - sn[a] * y;
-        A[i * m + q] = sn[a] * x + cs[a] * y;
-        const double vx = V[i * m + p], vy = V[i * m + q];
-        V[i * m + p] = cs[a] * vx - sn[a] * vy;
-        V[i * m + q] = sn[a] * vx + cs[a] * vy;
+        if (i < n) {
+          const double x = A[i * m + p], y = A[i * m + q];
+          A[i * m + p] = cs[a] * x - sn[a] * y;
+          A[i * m + q] = sn[a] * x + cs[a] * y;
+        }
+        if (i < m) {
+          const double vx = V[i * m + p], vy = V[i * m + q];
+          V[i * m + p] = cs[a] * vx - sn[a] * vy;
+          V[i * m + q] = sn[a] * vx + cs[a] * vy;
+        }
       }
       __syncthreads();
     }
@@ -443,7 +464,7 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
   double* nrm = red;
   for (int j = tid; j < m; j += nt) {
     double acc = 0.0;
-    for (int i = 0; i < m; ++i) acc = fma(A[i * m + j], A[i * m + j], acc);
+    for (int i = 0; i < n; ++i) acc = fma(A[i * m + j], A[i * m + j], acc);
     nrm[j] = sqrt(acc);
   }
   __syncthreads();
@@ -455,7 +476,7 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
   }
   __syncthreads();
   for (int j = tid; j < m; j += nt) S[rank[j]] = nrm[j];
-  for (int idx = tid; idx < m * m; idx += nt) {
+  for (int idx = tid; idx < n * m; idx += nt) {
     const int i = idx / m, j = idx % m;
     U[i * m + rank[j]] = nrm[j] > 0.0 ? A[idx] / nrm[j] : 0.0;
   }
@@ -472,7 +493,7 @@ __device__ void hestenes_body(double* __restrict__ A, int m, double* __restrict_
 __global__ void __launch_bounds__(1024) hestenes_kernel(double* __restrict__ A, int m, double* __restrict__ U,
                                                         double* __restrict__ V, double* __restrict__ S) {
   extern __shared__ double sh[];
-  hestenes_body(A, m, U, V, S, sh);
+  hestenes_body(A, m, m, U, V, S, sh);
 }
 
 // The same with A and V held in LDS (2 m^2 + 2560 doubles).
@@ -484,7 +505,7 @@ __global__ void __launch_bounds__(1024) hestenes_lds_kernel(const double* __rest
   double* V = A + m * m;
   for (int i = threadIdx.x; i < m * m; i += blockDim.x) A[i] = Ag[i];
   __syncthreads();
-  hestenes_body(A, m, U, V, S, sh);
+  hestenes_body(A, m, m, U, V, S, sh);
   __syncthreads();
   for (int i = threadIdx.x; i < m * m; i += blockDim.x) Vg[i] = V[i];
 }
@@ -561,17 +582,65 @@ static void tall_svd(const double* M, int64_t n, int m, double* Uo, double* S, d
   HIPC(hipGetLastError());
   // Q (into Uo) = Q1 W
   gemm(1, int(n), m, m, View{Q1, m, 1, 0}, View{W, m, 1, 0}, Uo, m, 0, 1.0, 0.0, ws, st);
-  // R^T = M^T Q (m x m) into G.  R = Q^T M has nearly orthogonal rows (Q
-  // comes from the eigenvectors of M^T M), so the one-sided Jacobi SVD of
-  // R^T = U' S V'^T converges in a sweep or two; then R = V' S U'^T.
-  gemm(1, m, m, n, View{M, 1, m, 0}, View{Uo, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
-  double* Up = W;                      // U' (right singular vectors of R)
-  double* Vp = V;                      // V' (left ones); V is free once W2 is formed
-  hestenes(G, m, Up, Vp, S, st);
-  HIPC(hipMemcpyAsync(Vo, Up, size_t(m) * m * sizeof(double), hipMemcpyDeviceToDevice, st));
-  // Uo <- Q V'  (through Q1 as scratch)
-  gemm(1, int(n), m, m, View{Uo, m, 1, 0}, View{Vp, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
+  // R = Q^T M  (m x m) into G
+  gemm(1, m, m, n, View{Uo, 1, m, 0}, View{M, m, 1, 0}, G, m, 0, 1.0, 0.0, ws, st);
+  double* UR = W;  // reuse
+  hestenes(G, m, UR, Vo, S, st);
+  // Uo <- Q U_R  (through Q1 as scratch)
+  gemm(1, int(n), m, m, View{Uo, m, 1, 0}, View{UR, m, 1, 0}, Q1, m, 0, 1.0, 0.0, ws, st);
   HIPC(hipMemcpyAsync(Uo, Q1, size_t(n) * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+
+// Thin SVD of a small n x m matrix in one workgroup: M is copied to LDS and
+// orthogonalised there by the one-sided Jacobi rotations directly (no Gram
+// pass), then the leading t triplets are written with those at or below
+// cut * sigma_max zeroed together with their vectors: U (n x t), S (t),
+// VT (t x m).  One launch instead of the Gram path's twenty, for the many
+// tiny blocks of small clusters.  LDS: A (max(n,m) x m), V (m x m), U (n x m)
+// and 2560 doubles of scratch.
+__global__ void __launch_bounds__(256) small_svd_kernel(const double* __restrict__ M, int n, int m, int t,
+                                                        double cut, double* __restrict__ Uo, double* __restrict__ So,
+                                                        double* __restrict__ VT) {
+  extern __shared__ double sh[];
+  const int nr = n > m ? n : m;
+  double* A = sh + 2560;
+  double* V = A + size_t(nr) * m;
+  double* U = V + size_t(m) * m;
+  double* S = U + size_t(n) * m;
+  for (int i = threadIdx.x; i < n * m; i += blockDim.x) A[i] = M[i];
+  __syncthreads();
+  hestenes_body(A, n, m, U, V, S, sh);
+  __syncthreads();
+  const double s0 = S[0];
+  for (int idx = threadIdx.x; idx < t * m; idx += blockDim.x) {
+    const int i = idx / m, col = idx % m;
+    const bool keep = i < m && s0 > 0.0 && S[i] > cut * s0;
+    VT[idx] = keep ? V[col * m + i] : 0.0;
+    if (col == 0) So[i] = keep ? S[i] : 0.0;
+  }
+  if (Uo)
+    for (int idx = threadIdx.x; idx < n * t; idx += blockDim.x) {
+      const int r = idx / t, j = idx % t;
+      const bool keep = j < m && s0 > 0.0 && S[j] > cut * s0;
+      Uo[idx] = keep ? U[r * m + j] : 0.0;
+    }
+}
+
+static size_t small_svd_lds(int64_t n, int m) {
+  const int64_t nr = n > m ? n : m;
+  return size_t(2560 + nr * m + int64_t(m) * m + n * m + m) * sizeof(double);
+}
+static bool small_svd_fits(int64_t n, int m) { return m <= 64 && n <= 4096 && small_svd_lds(n, m) <= 163840; }
+
+static void small_svd(const double* M, int64_t n, int m, int t, double cut, double* U, double* S, double* VT,
+                      hipStream_t st) {
+  KTimer _t("svd_small", st, 0.0, 8.0 * (double(n) * m + double(n) * t + double(t) * m));
+  const size_t shm = small_svd_lds(n, m);
+  if (shm > 65536)
+    HIPC(hipFuncSetAttribute(reinterpret_cast<const void*>(small_svd_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
+  hipLaunchKernelGGL(small_svd_kernel, dim3(1), dim3(256), shm, st, M, int(n), m, t, cut, U, S, VT);
+  HIPC(hipGetLastError());
 }
 
 // keep columns j with S[j] > cut * S[0]: Q[:, j] = U[:, j] (else 0)
@@ -584,6 +653,10 @@ __global__ void keep_cols_kernel(const double* __restrict__ U, const double* __r
 }
 
 void orth(const double* Y, int64_t n, int s, double cut, double* Q, Scratch& ws, hipStream_t st) {
+  if (small_svd_fits(n, s)) {  // Q = U with the dropped columns zeroed
+    small_svd(Y, n, s, s, cut, Q, ws.get(7, size_t(s)), ws.get(8, size_t(s) * s), st);
+    return;
+  }
   double* Ub = ws.get(6, size_t(n) * s);
   double* Sb = ws.get(7, size_t(s));
   double* Vb = ws.get(8, size_t(s) * s);
@@ -615,6 +688,10 @@ __global__ void svd_trunc_kernel(double* __restrict__ U, int64_t n, int m, int t
 
 void thin_svd_tall(const double* M, int64_t n, int m, int t, double cut, double* U, double* S,
                    double* VT, Scratch& ws, hipStream_t st) {
+  if (small_svd_fits(n, m) && t <= m) {
+    small_svd(M, n, m, t, cut, U, S, VT, st);
+    return;
+  }
   double* Ub = ws.get(6, size_t(n) * m);
   double* Sb = ws.get(7, size_t(m));
   double* Vb = ws.get(8, size_t(m) * m);
