@@ -307,6 +307,23 @@ tnb_status tnb_profile_query(const char* name, double* total_ms, int64_t* launch
                              double* bytes);
 tnb_status tnb_profile_names(char* buf, int64_t len);
 
+/* Device memory of the library.  By default hipMalloc/hipFree; with an
+ * allocator installed, every later allocation of a handle or of a call's
+ * scratch goes through alloc(bytes, user) (which returns NULL on failure:
+ * TNB_ENOMEM) and is returned through release(ptr, user) by the allocator
+ * that gave it, even after another one is installed.  The allocator must
+ * order the reuse of a released block after the work already queued on the
+ * stream of the call that released it (a stream-ordered caching allocator
+ * such as PyTorch's, used on the same stream, does).  NULL restores
+ * hipMalloc/hipFree.  Process-wide; installed allocators stay registered
+ * until the process ends.  Errors: TNB_EINVAL (a missing function). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*release)(void* ptr, void* user);
+  void* user;
+} tnb_allocator;
+tnb_status tnb_set_allocator(const tnb_allocator* a);
+
 /* Free a handle from tnb_build_clusters, tnb_contract_env or tnb_beam_create
  * (free dependants before what they reference).  NULL is ignored. */
 void tnb_destroy(void* handle);

@@ -21,6 +21,14 @@ class TnbEnvOpts(ctypes.Structure):
                 ("var_sweeps", c_int32), ("prec", c_int32)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class TnbAllocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", c_void_p)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "tnb_energies": (c_int32, [P(TnbInstance), c_void_p, c_int64, c_void_p, c_void_p]),
@@ -50,6 +58,7 @@ SIGNATURES = {
     "tnb_profile_enable": (c_int32, [c_int32]),
     "tnb_profile_query": (c_int32, [ctypes.c_char_p, P(c_double), P(c_int64), P(c_double), P(c_double)]),
     "tnb_profile_names": (c_int32, [ctypes.c_char_p, c_int64]),
+    "tnb_set_allocator": (c_int32, [P(TnbAllocator)]),
     "tnb_destroy": (None, [c_void_p]),
     "tnb_last_error": (ctypes.c_char_p, []),
 }

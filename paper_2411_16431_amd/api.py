@@ -293,6 +293,35 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
                 beam=beam, spin_marginals=marg)
 
 
+_ALLOC_KEEP = []
+
+
+def use_torch_allocator(on=True):
+    """Route the library's device memory through PyTorch's caching allocator
+    (tnb_set_allocator), on the current device and stream; on=False restores
+    hipMalloc.  Returns the number of allocations made through it so far
+    through the returned counter dict (tests)."""
+    import torch
+    if not on:
+        _check(L.lib().tnb_set_allocator(None))
+        return None
+    count = {"alloc": 0, "release": 0}
+
+    def _alloc(nbytes, user):
+        count["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  torch.cuda.current_stream())
+
+    def _release(ptr, user):
+        count["release"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = L.TnbAllocator(L.ALLOC_FN(_alloc), L.RELEASE_FN(_release), None)
+    _ALLOC_KEEP.append((a, _alloc, _release))   # the library may call them until the process ends
+    _check(L.lib().tnb_set_allocator(ctypes.byref(a)))
+    return count
+
+
 def autotune(measure, path=None):
     """tnb_autotune: measure (True) or reuse (False) the fastest launch
     variant per shape; path: JSON cache of the choices."""

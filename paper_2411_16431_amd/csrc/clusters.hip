@@ -147,39 +147,68 @@ __global__ void ising_energy_kernel(const int8_t* __restrict__ s, int64_t K, int
   out[kx] = acc;
 }
 
+// ---- device memory: hipMalloc or the caller's allocator ---------------------
+// Installed allocators are kept for the life of the process (blocks hold a
+// pointer to the one that gave them), so replacing one never strands a block.
+static std::mutex g_alloc_mu;
+static std::vector<std::unique_ptr<Allocator>> g_allocators;
+static const Allocator* g_current = nullptr;
+
+const Allocator* current_allocator() {
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  return g_current;
+}
+
+void* dev_alloc(size_t bytes, const Allocator** owner) {
+  const Allocator* a = current_allocator();
+  *owner = a;
+  void* p = nullptr;
+  if (!a) {
+    HIPC(hipMalloc(&p, bytes));
+    return p;
+  }
+  p = a->alloc(bytes, a->user);
+  if (!p) fail(TNB_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  return p;
+}
+
+void dev_free(void* p, const Allocator* owner) {
+  if (!owner) (void)hipFree(p);
+  else owner->release(p, owner->user);
+}
+
 static bool g_prof = false;
 static std::vector<ProfRec> g_recs;
 bool prof_on() { return g_prof; }
 void prof_push(const ProfRec& r) { g_recs.push_back(r); }
 
-const double* unit_weight() {
-  static double* ptr[64] = {nullptr};
+// A weight of 1 in device memory (the site weight of a cluster's empty side):
+// a constant of the code object, one copy per device.
+__device__ double g_unit64 = 1.0;
+__device__ float g_unit32 = 1.0f;
+
+// Address of a device symbol on the current device, looked up once per device.
+template <class T, class Get>
+static const T* per_device_symbol(Get get) {
+  static std::mutex mu;
+  static const T* ptr[64] = {nullptr};
   int dev = 0;
   HIPC(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) fail(TNB_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
   if (!ptr[dev]) {
-    double* p = nullptr;
-    HIPC(hipMalloc(reinterpret_cast<void**>(&p), sizeof(double)));
-    const double one = 1.0;
-    HIPC(hipMemcpy(p, &one, sizeof(double), hipMemcpyHostToDevice));
-    ptr[dev] = p;
+    void* p = nullptr;
+    HIPC(get(&p));
+    ptr[dev] = static_cast<const T*>(p);
   }
   return ptr[dev];
 }
 
+const double* unit_weight() {
+  return per_device_symbol<double>([](void** p) { return hipGetSymbolAddress(p, HIP_SYMBOL(g_unit64)); });
+}
 const float* unit_weight32() {
-  static float* ptr[64] = {nullptr};
-  int dev = 0;
-  HIPC(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) fail(TNB_EDEVICE, "device index out of range");
-  if (!ptr[dev]) {
-    float* p = nullptr;
-    HIPC(hipMalloc(reinterpret_cast<void**>(&p), sizeof(float)));
-    const float one = 1.0f;
-    HIPC(hipMemcpy(p, &one, sizeof(float), hipMemcpyHostToDevice));
-    ptr[dev] = p;
-  }
-  return ptr[dev];
+  return per_device_symbol<float>([](void** p) { return hipGetSymbolAddress(p, HIP_SYMBOL(g_unit32)); });
 }
 
 __global__ void to_f32_kernel(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
@@ -511,5 +540,22 @@ extern "C" tnb_status tnb_profile_names(char* buf, int64_t len) {
     }
     std::strncpy(buf, out.c_str(), size_t(len - 1));
     buf[len - 1] = '\0';
+  });
+}
+
+extern "C" tnb_status tnb_set_allocator(const tnb_allocator* a) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lock(g_alloc_mu);
+    if (!a) {
+      g_current = nullptr;
+      return;
+    }
+    if (!a->alloc || !a->release) fail(TNB_EINVAL, "allocator needs both alloc and release");
+    auto al = std::make_unique<Allocator>();
+    al->alloc = a->alloc;
+    al->release = a->release;
+    al->user = a->user;
+    g_current = al.get();
+    g_allocators.push_back(std::move(al));
   });
 }

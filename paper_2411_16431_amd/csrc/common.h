@@ -33,31 +33,55 @@ inline void hip_check(hipError_t e, const char* what) {
 void set_error(const std::string& msg);
 void clear_error();
 
-// Owning device allocation (hipMallocAsync-free: plain hipMalloc, freed on
-// destruction after the device is idle for this buffer's stream users).
+// Device memory of the library: hipMalloc/hipFree, or the caller's
+// allocator when one is installed (tnb_set_allocator).  A block is returned
+// to the allocator that gave it.
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*release)(void*, void*) = nullptr;
+  void* user = nullptr;
+};
+const Allocator* current_allocator();  // nullptr: hipMalloc / hipFree
+void* dev_alloc(size_t bytes, const Allocator** owner);
+void dev_free(void* p, const Allocator* owner);
+
+// Owning device allocation, freed on destruction.  With hipFree the runtime
+// waits for the device; a caller's allocator must order reuse after the
+// work queued on the library's streams (a stream-ordered caching allocator
+// on the same stream does).
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  const Allocator* owner = nullptr;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), owner(o.owner) { o.p = nullptr; o.n = 0; o.owner = nullptr; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      owner = o.owner;
+      o.p = nullptr;
+      o.n = 0;
+      o.owner = nullptr;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
     n = count;
-    if (count) HIPC(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    if (count) p = static_cast<T*>(dev_alloc(count * sizeof(T), &owner));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, owner);
     p = nullptr;
     n = 0;
+    owner = nullptr;
   }
   void upload(const T* host, size_t count, hipStream_t s) {
     if (count > n) alloc(count);

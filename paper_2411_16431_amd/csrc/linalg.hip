@@ -369,32 +369,68 @@ __global__ void inv_sqrt_weights_kernel(const double* __restrict__ V, const doub
 }
 
 // One-sided Jacobi SVD (Hestenes; Golub & Van Loan Sec. 8.6.3) of a small
-// n x m matrix A (row-major, overwritten by U*S; room for max(n, m) rows):
-// rotations orthogonalise the columns pairwise, round-robin over disjoint
-// pairs.  Singular values are accurate to eps * sigma_max.  Outputs sorted
-// descending: S[m], U (n x m, columns of A normalised; zero for sigma = 0),
-// V (m x m).  A and V are the working matrices (global memory, or LDS in the
-// _lds variants); sh is 2560 doubles of LDS scratch.
-__device__ void hestenes_body(double* __restrict__ A, int n, int m, double* __restrict__ U, double* __restrict__ V,
-                              double* __restrict__ S, double* __restrict__ sh) {
-  double* cs = sh;           // [512]
-  double* sn = sh + 512;     // [512]
-  int* pp = reinterpret_cast<int*>(sh + 1024);
-  int* qq = pp + 512;
-  double* red = sh + 1536;   // [1024]
+// n x m matrix A, overwritten by U*S: rotations orthogonalise the columns
+// pairwise, round-robin over disjoint pairs.  Singular values are accurate to
+// eps * sigma_max.  Outputs sorted descending: S[m], U (n x m row-major,
+// columns of A normalised; zero for sigma = 0), V (m x m row-major).
+//
+// CM selects the working layout of A and V: column-major with leading
+// dimension ld (LDS: a column is contiguous, so the lanes of a pair read
+// consecutive words; ld is odd so that the pairs of a wave start on different
+// banks), or row-major with ld = m (the global-memory variant).  A needs room
+// for max(n, m) rows.  sh is 64 doubles of LDS scratch; nrm and rank hold m
+// entries each.
+//
+// A column pair is owned by a group of L lanes for the whole round: the group
+// forms the three dot products (strided partial sums, then a butterfly that
+// leaves the same sum on every lane), derives the rotation and applies it to
+// the rows it read, so one barrier per round suffices.  Columns whose squared
+// norm is at most 1e-28 ||A||_F^2 (rank deficiency: the n < m columns beyond
+// the rank, or a rank-deficient R) are left alone and do not count towards
+// convergence; their singular values are at the rounding level.
+template <bool CM>
+__device__ void hestenes_body(double* __restrict__ A, int n, int m, int ld, double* __restrict__ U,
+                              double* __restrict__ V, double* __restrict__ S, double* __restrict__ sh,
+                              double* __restrict__ nrm, int* __restrict__ rank) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int mm = m + (m & 1);
-  for (int idx = tid; idx < m * m; idx += nt) V[idx] = (idx / m == idx % m) ? 1.0 : 0.0;
-  __syncthreads();
+  const int mm = m + (m & 1), np = mm / 2;
+  const int vld = CM ? (m | 1) : m;
+  auto at = [&](double* X, int xld, int i, int j) -> double& { return CM ? X[size_t(j) * xld + i] : X[size_t(i) * m + j]; };
+  for (int idx = tid; idx < m * m; idx += nt) at(V, vld, idx / m, idx % m) = (idx / m == idx % m) ? 1.0 : 0.0;
+  // block reductions through sh: wave partials in sh[0..15], result in sh[32]
+  auto block_sum = [&](double x, bool take_max) -> double {
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_xor(x, o, 64);
+      x = take_max ? fmax(x, y) : x + y;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) sh[tid >> 6] = x;
+    __syncthreads();
+    if (tid == 0) {
+      double r = sh[0];
+      for (int w = 1; w < (nt + 63) / 64; ++w) r = take_max ? fmax(r, sh[w]) : r + sh[w];
+      sh[32] = r;
+    }
+    __syncthreads();
+    return sh[32];
+  };
+  double f2 = 0.0;
+  for (int idx = tid; idx < n * m; idx += nt) {
+    const double x = at(A, ld, idx / m, idx % m);
+    f2 = fma(x, x, f2);
+  }
+  const double tiny = 1e-28 * block_sum(f2, false);
+  int L = 16;
+  while (L > 1 && np * L > nt) L >>= 1;
+  const int groups = nt / L;                       // pairs handled at once
+  const int iters = (np + groups - 1) / groups;    // the same count on every lane
+  const int sub = tid % L;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double worst = 0.0;
     for (int round = 0; round < mm - 1; ++round) {
-      // 16 lanes per column pair: strided partial dot products, then a
-      // butterfly over the 16 lanes (the same order on every lane)
-      const int sub = tid & 15;
-      for (int a0 = tid >> 4; a0 < (mm / 2 + 15) / 16 * 16; a0 += nt >> 4) {
-        const int a = a0;
-        const bool act = a < mm / 2;
+      for (int it = 0; it < iters; ++it) {
+        const int a = it * groups + tid / L;
+        const bool act = a < np;
         int p = 0, q = m;
         if (act) {
           const int p1 = (a == 0) ? 0 : 1 + (a - 1 + round) % (mm - 1);
@@ -402,73 +438,48 @@ __device__ void hestenes_body(double* __restrict__ A, int n, int m, double* __re
           p = p1 < p2 ? p1 : p2;
           q = p1 < p2 ? p2 : p1;
         }
+        const bool real = act && q < m;
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (act && q < m)
-          for (int i = sub; i < n; i += 16) {
-            const double x = A[i * m + p], y = A[i * m + q];
+        if (real)
+          for (int i = sub; i < n; i += L) {
+            const double x = at(A, ld, i, p), y = at(A, ld, i, q);
             al = fma(x, x, al);
             be = fma(y, y, be);
             ga = fma(x, y, ga);
           }
-        for (int o = 8; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, 16);
-          be += __shfl_xor(be, o, 16);
-          ga += __shfl_xor(ga, o, 16);
+        for (int o = L / 2; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, L);
+          be += __shfl_xor(be, o, L);
+          ga += __shfl_xor(ga, o, L);
         }
-        if (act && sub == 0) {
-          double c = 1.0, sv = 0.0;
-          if (q < m && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sv = c * t;
-            const double r = fabs(ga) / sqrt(al * be);
-            worst = fmax(worst, r);
+        if (real && al > tiny && be > tiny && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sv = c * t;
+          worst = fmax(worst, fabs(ga) / sqrt(al * be));
+          for (int i = sub; i < n; i += L) {
+            const double x = at(A, ld, i, p), y = at(A, ld, i, q);
+            at(A, ld, i, p) = c * x - sv * y;
+            at(A, ld, i, q) = sv * x + c * y;
           }
-          pp[a] = p;
-          qq[a] = q;
-          cs[a] = c;
-          sn[a] = sv;
+          for (int i = sub; i < m; i += L) {
+            const double vx = at(V, vld, i, p), vy = at(V, vld, i, q);
+            at(V, vld, i, p) = c * vx - sv * vy;
+            at(V, vld, i, q) = sv * vx + c * vy;
+          }
         }
       }
-      __syncthreads();
-      const int nr = n > m ? n : m;
-      for (int idx = tid; idx < (mm / 2) * nr; idx += nt) {
-        const int a = idx / nr, i = idx % nr;
-        const int p = pp[a], q = qq[a];
-        if (q >= m || sn[a] == 0.0) continue;
-        if (i < n) {
-          const double x = A[i * m + p], y = A[i * m + q];
-          A[i * m + p] = cs[a] * x - sn[a] * y;
-          A[i * m + q] = sn[a] * x + cs[a] * y;
-        }
-        if (i < m) {
-          const double vx = V[i * m + p], vy = V[i * m + q];
-          V[i * m + p] = cs[a] * vx - sn[a] * vy;
-          V[i * m + q] = sn[a] * vx + cs[a] * vy;
-        }
-      }
-      __syncthreads();
+      __syncthreads();  // the next round pairs the columns differently
     }
-    red[tid] = worst;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-      __syncthreads();
-    }
-    const bool done = red[0] <= 1e-15;
-    __syncthreads();
-    if (done) break;
+    if (block_sum(worst, true) <= 1e-15) break;
   }
   // column norms, sort descending (ties by index), normalise
-  double* nrm = red;
   for (int j = tid; j < m; j += nt) {
     double acc = 0.0;
-    for (int i = 0; i < n; ++i) acc = fma(A[i * m + j], A[i * m + j], acc);
+    for (int i = 0; i < n; ++i) acc = fma(at(A, ld, i, j), at(A, ld, i, j), acc);
     nrm[j] = sqrt(acc);
   }
   __syncthreads();
-  int* rank = reinterpret_cast<int*>(cs);
   for (int j = tid; j < m; j += nt) {
     int r = 0;
     for (int o = 0; o < m; ++o) r += (nrm[o] > nrm[j]) || (nrm[o] == nrm[j] && o < j);
@@ -478,34 +489,38 @@ __device__ void hestenes_body(double* __restrict__ A, int n, int m, double* __re
   for (int j = tid; j < m; j += nt) S[rank[j]] = nrm[j];
   for (int idx = tid; idx < n * m; idx += nt) {
     const int i = idx / m, j = idx % m;
-    U[i * m + rank[j]] = nrm[j] > 0.0 ? A[idx] / nrm[j] : 0.0;
+    U[size_t(i) * m + rank[j]] = nrm[j] > 0.0 ? at(A, ld, i, j) / nrm[j] : 0.0;
   }
   __syncthreads();
-  // V columns permuted through A as scratch
-  for (int idx = tid; idx < m * m; idx += nt) A[idx] = V[idx];
+  // V columns permuted through A as scratch; V leaves row-major (m x m)
+  for (int idx = tid; idx < m * m; idx += nt) A[idx] = at(V, vld, idx / m, idx % m);
   __syncthreads();
-  for (int idx = tid; idx < m * m; idx += nt) {
-    const int i = idx / m, j = idx % m;
-    V[i * m + rank[j]] = A[idx];
-  }
+  for (int idx = tid; idx < m * m; idx += nt) V[size_t(idx / m) * m + rank[idx % m]] = A[idx];
 }
 
 __global__ void __launch_bounds__(1024) hestenes_kernel(double* __restrict__ A, int m, double* __restrict__ U,
                                                         double* __restrict__ V, double* __restrict__ S) {
-  extern __shared__ double sh[];
-  hestenes_body(A, m, m, U, V, S, sh);
+  __shared__ double sh[64], nrm[1024];
+  __shared__ int rank[1024];
+  hestenes_body<false>(A, m, m, m, U, V, S, sh, nrm, rank);
 }
 
-// The same with A and V held in LDS (2 m^2 + 2560 doubles).
+// The same with A and V held in LDS, column-major with leading dimension
+// m | 1, after 64 + 2 m doubles of scratch.
+static size_t hestenes_lds_bytes(int m) { return (64 + 2 * size_t(m) + 2 * size_t(m | 1) * m) * sizeof(double); }
+
 __global__ void __launch_bounds__(1024) hestenes_lds_kernel(const double* __restrict__ Ag, int m,
                                                             double* __restrict__ U, double* __restrict__ Vg,
                                                             double* __restrict__ S) {
   extern __shared__ double sh[];
-  double* A = sh + 2560;
-  double* V = A + m * m;
-  for (int i = threadIdx.x; i < m * m; i += blockDim.x) A[i] = Ag[i];
+  const int ld = m | 1;
+  double* nrm = sh + 64;
+  int* rank = reinterpret_cast<int*>(nrm + m);
+  double* A = nrm + 2 * m;
+  double* V = A + size_t(ld) * m;
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) A[size_t(i % m) * ld + i / m] = Ag[i];
   __syncthreads();
-  hestenes_body(A, m, m, U, V, S, sh);
+  hestenes_body<true>(A, m, m, ld, U, V, S, sh, nrm, rank);
   __syncthreads();
   for (int i = threadIdx.x; i < m * m; i += blockDim.x) Vg[i] = V[i];
 }
@@ -513,12 +528,12 @@ __global__ void __launch_bounds__(1024) hestenes_lds_kernel(const double* __rest
 static void hestenes(double* A, int m, double* U, double* V, double* S, hipStream_t st) {
   if (m > 1000) fail(TNB_EUNSUPPORTED, "SVD limited to 1000 x 1000");
   KTimer _t("svd_small", st, 0.0, 24.0 * m * m);
-  if (lds_fits(m)) {
-    const size_t shm = (2560 + 2 * size_t(m) * m) * sizeof(double);
+  if (hestenes_lds_bytes(m) <= 163840) {
+    const size_t shm = hestenes_lds_bytes(m);
     allow_lds(hestenes_lds_kernel, shm);
     hipLaunchKernelGGL(hestenes_lds_kernel, dim3(1), dim3(1024), shm, st, A, m, U, V, S);
   } else {
-    hipLaunchKernelGGL(hestenes_kernel, dim3(1), dim3(1024), 2560 * sizeof(double), st, A, m, U, V, S);
+    hipLaunchKernelGGL(hestenes_kernel, dim3(1), dim3(1024), 0, st, A, m, U, V, S);
   }
   HIPC(hipGetLastError());
 }
@@ -602,14 +617,16 @@ __global__ void __launch_bounds__(256) small_svd_kernel(const double* __restrict
                                                         double cut, double* __restrict__ Uo, double* __restrict__ So,
                                                         double* __restrict__ VT) {
   extern __shared__ double sh[];
-  const int nr = n > m ? n : m;
-  double* A = sh + 2560;
-  double* V = A + size_t(nr) * m;
-  double* U = V + size_t(m) * m;
+  const int nr = n > m ? n : m, ld = nr | 1;
+  double* nrm = sh + 64;
+  int* rank = reinterpret_cast<int*>(nrm + m);
+  double* A = nrm + 2 * m;                 // column-major, ld x m
+  double* V = A + size_t(ld) * m;          // column-major, (m | 1) x m
+  double* U = V + size_t(m | 1) * m;
   double* S = U + size_t(n) * m;
-  for (int i = threadIdx.x; i < n * m; i += blockDim.x) A[i] = M[i];
+  for (int i = threadIdx.x; i < n * m; i += blockDim.x) A[size_t(i % m) * ld + i / m] = M[i];
   __syncthreads();
-  hestenes_body(A, n, m, U, V, S, sh);
+  hestenes_body<true>(A, n, m, ld, U, V, S, sh, nrm, rank);
   __syncthreads();
   const double s0 = S[0];
   for (int idx = threadIdx.x; idx < t * m; idx += blockDim.x) {
@@ -628,7 +645,7 @@ __global__ void __launch_bounds__(256) small_svd_kernel(const double* __restrict
 
 static size_t small_svd_lds(int64_t n, int m) {
   const int64_t nr = n > m ? n : m;
-  return size_t(2560 + nr * m + int64_t(m) * m + n * m + m) * sizeof(double);
+  return size_t(64 + 2 * m + (nr | 1) * m + int64_t(m | 1) * m + n * m + m) * sizeof(double);
 }
 static bool small_svd_fits(int64_t n, int m) { return m <= 64 && n <= 4096 && small_svd_lds(n, m) <= 163840; }
 

@@ -31,3 +31,16 @@ def test_header_declares_the_boundary_calls():
     for name in ("tnb_build_clusters", "tnb_contract_env", "tnb_marginals", "tnb_branch_step",
                  "tnb_energies"):
         assert name in decl
+
+
+def test_set_allocator_checks_its_argument_on_the_host():
+    # installing or clearing an allocator touches no device
+    import ctypes
+    import paper_2411_16431_amd as pk
+    if not os.path.exists(pk.library_path()):
+        pytest.skip("libtnbb.so not built")
+    from paper_2411_16431_amd import _lib
+    lib = _lib.lib()
+    half = _lib.TnbAllocator(_lib.ALLOC_FN(lambda n, u: None), ctypes.cast(None, _lib.RELEASE_FN), None)
+    assert lib.tnb_set_allocator(ctypes.byref(half)) == -1     # TNB_EINVAL
+    assert lib.tnb_set_allocator(None) == 0
