@@ -37,8 +37,8 @@ WORKLOADS = {
 
 # MI355X: FP64 vector and FP64 MFMA peaks are equal; FP32 MFMA (dense) and FP32 vector are 157.3
 PEAK = {"alu_fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
-MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_G2", "medf_out", "medf_lbin", "medf_lacc", "renv_V", "adj_v",
-                "site_apply", "site_applyT", "site_left", "gemm"}
+MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_Y2g", "medf_W2g", "medf_G2", "medf_out", "medf_lbin", "medf_lacc",
+                "renv_V", "adj_v", "site_apply", "site_applyT", "site_left", "gemm"}
 
 
 def peak_of(name):
@@ -50,7 +50,10 @@ def unit_class(name):
     return "mfma" if name.replace("_f32", "") in MFMA_KERNELS else "alu"
 # library timer -> the kernel instance rocprofv3 reports for it
 ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0, double>", "medf_W2": "medf_bin_pipe<1, 1, 0, double>",
-                "medf_lbin": "medf_bin_pipe<0, 1, 1, double>"}
+                "medf_lbin": "medf_bin_pipe<0, 1, 1, double>", "medf_G2": "gemm_mfma_kernel<1>",
+                "medf_out": "gemm_mfma_kernel<2>", "medf_Y2g": "gemm_mfma_kernel<3>",
+                "medf_W2g": "gemm_mfma_kernel<4>", "medf_Y2w": "medf_wsum_kernel<0>",
+                "medf_W2w": "medf_wsum_kernel<1>"}
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
@@ -365,8 +368,8 @@ def main():
                 "avg_ms": ms / n, "launches_per_step": n / args.steps,
                 "share_of_step": ms / args.steps / ms_step}
     counts = {"site": (prof.get("site_apply", (0, 0))[1] + prof.get("site_applyT", (0, 0))[1]) / args.steps,
-              "med": (prof.get("med_apply", (0, 0))[1] + prof.get("med_applyT", (0, 0))[1]
-                      + prof.get("medf_Y2", (0, 0))[1] + prof.get("medf_W2", (0, 0))[1]) / args.steps}
+              "med": sum(prof.get(nm, (0, 0))[1] for nm in ("med_apply", "med_applyT", "medf_Y2", "medf_W2",
+                                                                "medf_Y2g", "medf_W2g")) / args.steps}
     adj = adjoint_compare(pk, torch, res["env"], wl, inst)
     f32 = None if args.no_f32 else fp32_compare(pk, torch, inst, wl, env_kw, res, args.steps)
     print("fp32 comparison done", file=sys.stderr, flush=True)

@@ -281,12 +281,14 @@ tnb_status tnb_row_moments(tnb_beam* beam, double* d_m1, int64_t m1_len, double*
 tnb_status tnb_row_moments_per_branch(tnb_beam* beam, double* d_m1, int64_t m1_len, tnb_stream stream);
 
 /* Autotuner of kernel launch variants.  Some diagram stages have several
- * launch variants that give bit-identical results and differ only in how the
- * work is tiled over workgroups (e.g. sketch columns per workgroup of the
- * binned mediating kernel).  mode 1: the first launch of every new shape
- * times each candidate once with HIP events on the launch stream and keeps
- * the fastest; mode 0: use the stored choices and the default variant for
- * unseen shapes.  path (may be NULL: in memory only) names a JSON file of
+ * launch variants that compute the same sums and differ in how the work is
+ * tiled over workgroups (sketch columns per workgroup of the binned mediating
+ * kernel: bit-identical results) or in the order of their additions (the
+ * grouped mediating kernel, which sums the items of one weight group before
+ * weighting them: equal up to rounding).  mode 1: the first launch of every
+ * new shape times each candidate once with HIP events on the launch stream,
+ * keeps the fastest and leaves its result; mode 0: use the stored choices and
+ * the default variant for unseen shapes.  path (may be NULL: in memory only) names a JSON file of
  * {"shape": variant} that is read now and rewritten after every new choice.
  * Process-wide; calls that tune concurrently are serialised.
  * Errors: TNB_EINVAL (mode). */

@@ -69,8 +69,10 @@ struct Operand {
 // C(m, n) = alpha * sum_k A(m, k) B(k, n) + beta * C(m, n) for every batch,
 // on the FP64 matrix cores (16x16x4 MFMA), 128 x 64 output tiles, each tile
 // owned by one workgroup and summed over all of K in order (deterministic).
+// tag selects a separately named kernel instance (same code): 0 general,
+// 1 .. 5 the mediating diagram's G2, out, Y2, W2 and left-transfer products.
 void gemm_mfma(int batch, int M, int N, int K, const Operand& A, const Operand& B, double* C, Ix cr, Ix cc,
-               int64_t cbs, double alpha, double beta, hipStream_t s, const char* timer = "gemm_mfma");
+               int64_t cbs, double alpha, double beta, hipStream_t s, const char* timer = "gemm_mfma", int tag = 0);
 
 }  // namespace la
 }  // namespace tnb
