@@ -49,10 +49,11 @@ def peak_of(name):
 def unit_class(name):
     return "mfma" if name.replace("_f32", "") in MFMA_KERNELS else "alu"
 # library timer -> the kernel instance rocprofv3 reports for it
+# (a prefix where the timer's launches use several tile variants of one kernel)
 ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0, double>", "medf_W2": "medf_bin_pipe<1, 1, 0, double>",
-                "medf_lbin": "medf_bin_pipe<0, 1, 1, double>", "medf_G2": "gemm_mfma_kernel<1>",
-                "medf_out": "gemm_mfma_kernel<2>", "medf_Y2g": "gemm_mfma_kernel<3>",
-                "medf_W2g": "gemm_mfma_kernel<4>", "medf_Y2w": "medf_wsum_kernel<0>",
+                "medf_lbin": "medf_bin_pipe<0, 1, 1, double>", "medf_G2": "gemm_mfma_kernel<1,",
+                "medf_out": "gemm_mfma_kernel<2,", "medf_Y2g": "gemm_mfma_kernel<3,",
+                "medf_W2g": "gemm_mfma_kernel<4,", "medf_Y2w": "medf_wsum_kernel<0>",
                 "medf_W2w": "medf_wsum_kernel<1>"}
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and

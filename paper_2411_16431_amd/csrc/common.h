@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <utility>
 #include <vector>
@@ -44,6 +45,10 @@ struct Allocator {
 const Allocator* current_allocator();  // nullptr: hipMalloc / hipFree
 void* dev_alloc(size_t bytes, const Allocator** owner);
 void dev_free(void* p, const Allocator* owner);
+
+// Launch-variant autotuner (tnb_autotune): runs run(v) for the stored, or
+// (when measuring) the fastest, of n variants of `key`; returns the choice.
+int autotune_pick(const std::string& key, int n, const std::function<void(int)>& run, hipStream_t st);
 
 // Owning device allocation, freed on destruction.  With hipFree the runtime
 // waits for the device; a caller's allocator must order reuse after the

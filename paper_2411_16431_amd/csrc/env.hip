@@ -1335,6 +1335,9 @@ Tuner& tuner() {
   static Tuner t;
   return t;
 }
+int autotune_pick(const std::string& key, int n, const std::function<void(int)>& run, hipStream_t st) {
+  return tuner().pick(key, n, run, st);
+}
 
 // ---- the plain accumulations as batched GEMMs ------------------------------
 // Where the item index of an accumulation splits into two disjoint bit sets,
