@@ -14,4 +14,6 @@ Modules
              truncation, log Z.
   search  -- Sec. III.A, Eq. (7)-(9): conditional marginals from the
              boundary MPS and branch and bound with boundary merging.
+  droplets -- Sec. III.A, Fig. 4: excitations above each main branch from
+             the members its merge discards.
 """

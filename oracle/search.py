@@ -127,11 +127,16 @@ def boundary_key_masks(net, n_fixed):
     return out
 
 
-def solve(inst, beta, env, M, K=8, merge=True, trace=False):
-    """Full search; returns dict with the K lowest states and diagnostics."""
+def solve(inst, beta, env, M, K=8, merge=True, trace=False, droplets=None):
+    """Full search; returns dict with the K lowest states and diagnostics.
+    droplets: a droplets.DropletOptions to keep the excitations found by the
+    merge (Fig. 4) with every branch; they are returned per output state."""
+    from . import droplets as dl
     net = env.net
     R, C = net.R, net.C
     ncell = R * C
+    bonds = dl.cluster_bonds(net.P) if droplets is not None else None
+    drop = [[]]
     X = np.zeros((1, ncell), dtype=np.int64)
     logp = np.zeros(1)
     L = np.ones((1, 1))
@@ -182,6 +187,11 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
             keep = win[:M]
             if len(win) > M:
                 pd_log = max(pd_log, sc[win[M]])
+            if droplets is not None:
+                if merge and masks:
+                    drop = dl.merge_step(inst, net.P, bonds, droplets, X, drop, n, bb, xx, sc, keys, keep)
+                else:
+                    drop = [list(drop[bb[i]]) for i in keep]
             rec = dict(n=n, candidates=len(bb), groups=len(win), kept=len(keep))
             if trace:
                 # selection margins (R7, R10): the score gap between the last
@@ -201,6 +211,8 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
                 rec["X"][:, n] = xx[keep]
                 rec["logp"] = sc[keep].copy()
                 rec["p_d_log"] = pd_log
+                if droplets is not None:
+                    rec["droplets"] = [list(d) for d in drop]
             steps.append(rec)
             Xn = X[bb[keep]].copy()
             Xn[:, n] = xx[keep]
@@ -224,8 +236,12 @@ def solve(inst, beta, env, M, K=8, merge=True, trace=False):
         if len(out) == K:
             break
     out = np.array(out, dtype=np.int64)
-    return dict(states=states[out], energies=E[out], logp=logp[out], X=X[out],
-                p_d_log=pd_log, steps=steps, all_states=states, all_logp=logp)
+    res = dict(states=states[out], energies=E[out], logp=logp[out], X=X[out],
+               p_d_log=pd_log, steps=steps, all_states=states, all_logp=logp)
+    if droplets is not None:
+        res["droplets"] = [drop[i] for i in out]
+        res["all_droplets"] = drop
+    return res
 
 
 def root_marginal_check(net, env):
