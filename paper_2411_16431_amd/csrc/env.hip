@@ -1722,7 +1722,7 @@ struct Zipper {
                   la::Ix{uint32_t(s), int64_t(md.db2) * f.nHL * Db * s, 1}};
     la::gemm_mfma(sp.nh, M, N, Kd, a, b, Cp, la::Ix{uint32_t(Dg), int64_t(md.drd) * Dg * s, s},
                   la::Ix{uint32_t(s), int64_t(Dg) * s, 1}, int64_t(sp.nrest) * md.drd * Dg * s, 1.0, 0.0, st,
-                  "medf_G2", 1);
+                  "medf_G2g", 1);
     {
       KTimer _t("medf_perm", st, 0.0, 16.0 * double(nC));
       hipLaunchKernelGGL(scatter_out_kernel, dim3(blocks(nC)), dim3(256), 0, st, Cp, sp, 1, 0u,
@@ -1825,7 +1825,7 @@ struct Zipper {
                   la::Ix{uint32_t(s), int64_t(md.db2) * f.nHR * Db * s, 1}};
     la::gemm_mfma(sp.nh, M, N, Kd, a, b, Cp, la::Ix{uint32_t(Da), int64_t(md.drd) * Da * s, s},
                   la::Ix{uint32_t(s), int64_t(Da) * s, 1}, int64_t(sp.nrest) * md.drd * Da * s, 1.0, 0.0, st,
-                  "medf_out", 2);
+                  "medf_outg", 2);
     {
       KTimer _t("medf_perm", st, 0.0, 16.0 * double(nC));
       hipLaunchKernelGGL(scatter_out_kernel, dim3(blocks(nC)), dim3(256), 0, st, Cp, sp, md.drd, md.pos_d_rho,
