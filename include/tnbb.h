@@ -326,6 +326,44 @@ typedef struct {
 } tnb_allocator;
 tnb_status tnb_set_allocator(const tnb_allocator* a);
 
+/* Excitations above each branch from the boundary merge (Sec. III.A, Fig. 4).
+ * When tnb_branch_step groups candidates by their boundary, the group's most
+ * probable member is kept and every other member differs from it only away
+ * from the boundary: that difference (a flip set over clusters, with its
+ * energy dE = E(branch with the set flipped) - E(branch) of Eq. 1) is an
+ * excitation of the kept branch, which also takes over the other members'
+ * excitations (composed with the difference; energies add exactly).
+ * Kept per branch: among its own excitations and those from the first
+ * max_losers members (by score, then parent, then cluster value), the ones
+ * with at most max_cells flipped clusters, dE <= max_dE and (connected_only)
+ * flipped clusters connected through couplings, visited by increasing dE
+ * (ties: the flip set as a sequence of (cluster, mask) pairs) and accepted
+ * while at Hamming distance >= min_hamming from every accepted one, at most
+ * max_droplets.  Limits: max_droplets <= 16, max_losers <= 8, max_cells <= 64,
+ * min_hamming >= 1. */
+typedef struct {
+  int32_t max_droplets;    /* 0 switches the bookkeeping off */
+  int32_t max_losers;
+  int32_t min_hamming;
+  int32_t max_cells;
+  double max_dE;
+  int32_t connected_only;
+} tnb_droplet_opts;
+
+/* Switch the bookkeeping on (or off with NULL or max_droplets = 0) for a beam
+ * that has taken no step yet.  Errors: TNB_EINVAL (handle, limits, steps
+ * already taken), TNB_ENOMEM. */
+tnb_status tnb_beam_droplets_enable(tnb_beam* beam, const tnb_droplet_opts* opts);
+
+/* The excitations of branch i of the current beam (0 <= i < npar, the order
+ * of tnb_beam_export): up to max_count states d_states [max_count][n_spins]
+ * (int8 +-1, 0 for spins of unfixed clusters; the branch's state with the
+ * flip set applied) and their dE (d_dE, FP64), by increasing dE; *count
+ * receives the number written.  Queued on `stream` and synchronised.
+ * Errors: TNB_EINVAL (handle, bookkeeping off, i, outputs). */
+tnb_status tnb_beam_droplets(const tnb_beam* beam, int32_t i, int32_t max_count, int8_t* d_states,
+                             double* d_dE, int32_t* count, tnb_stream stream);
+
 /* Free a handle from tnb_build_clusters, tnb_contract_env or tnb_beam_create
  * (free dependants before what they reference).  NULL is ignored. */
 void tnb_destroy(void* handle);

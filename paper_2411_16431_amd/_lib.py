@@ -25,6 +25,11 @@ ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
 RELEASE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
 
 
+class TnbDropletOpts(ctypes.Structure):
+    _fields_ = [("max_droplets", c_int32), ("max_losers", c_int32), ("min_hamming", c_int32),
+                ("max_cells", c_int32), ("max_dE", ctypes.c_double), ("connected_only", c_int32)]
+
+
 class TnbAllocator(ctypes.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", c_void_p)]
 
@@ -49,6 +54,8 @@ SIGNATURES = {
     "tnb_branch_step": (c_int32, [c_void_p, P(c_double), c_void_p]),
     "tnb_beam_export": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_beam_lowest": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
+    "tnb_beam_droplets_enable": (c_int32, [c_void_p, P(TnbDropletOpts)]),
+    "tnb_beam_droplets": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_select_lowest": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, P(c_int32),
                                     c_void_p]),
     "tnb_row_layout": (c_int32, [c_void_p, P(c_int32), P(c_int32), c_void_p, c_void_p, c_int32]),

@@ -165,6 +165,24 @@ class Beam(_Handle):
         _check(L.lib().tnb_beam_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
+    def enable_droplets(self, max_droplets=16, max_losers=8, min_hamming=1, max_cells=64, max_dE=math.inf,
+                        connected_only=True):
+        """tnb_beam_droplets_enable: keep the excitations the boundary merge
+        finds above every branch (before the first step)."""
+        o = L.TnbDropletOpts(int(max_droplets), int(max_losers), int(min_hamming), int(max_cells), float(max_dE),
+                             1 if connected_only else 0)
+        _check(L.lib().tnb_beam_droplets_enable(self._h, ctypes.byref(o)))
+
+    def droplets(self, i, n_spins, max_count=16):
+        """tnb_beam_droplets: (states int8 [k, N], dE [k]) of branch i."""
+        import torch
+        st = torch.empty((max(max_count, 1), n_spins), dtype=torch.int8, device="cuda")
+        dE = torch.empty(max(max_count, 1), dtype=torch.float64, device="cuda")
+        cnt = ctypes.c_int32()
+        _check(L.lib().tnb_beam_droplets(self._h, int(i), int(max_count), ctypes.c_void_p(st.data_ptr()),
+                                         ctypes.c_void_p(dE.data_ptr()), ctypes.byref(cnt), _stream()))
+        return st[:cnt.value], dE[:cnt.value]
+
     def marginals(self, mode="vector"):
         """tnb_marginals: 'vector' p_b(x) [parents, d]; 'spin' <s_i>_b of the
         next cluster [parents, k]; 'adjoint' <s_i>_b of the unfixed row spins

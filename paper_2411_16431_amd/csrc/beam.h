@@ -81,6 +81,14 @@ struct tnb_beam {
   tnb::DevBuf<int8_t> sel_states;
   tnb::DevBuf<double> sel_E;
   tnb::DevBuf<int> sel_dup;
+  // droplets: per branch its partial energy and up to DMAX excitations, each
+  // a sorted list of (cluster, XOR mask) pairs (at most SMAX) and its dE
+  tnb_droplet_opts dopt{};
+  tnb::DevBuf<double> Ep, Epn;
+  tnb::DevBuf<int32_t> dcnt, dcntn, dlen, dlenn, dcell, dcelln;
+  tnb::DevBuf<uint32_t> dmask, dmaskn;
+  tnb::DevBuf<double> dEv, dEvn;
+  tnb::DevBuf<uint32_t> bonded;  // per cluster: coupled king neighbours, bit (dr+1)*3 + (dc+1)
 };
 
 namespace tnb {
@@ -104,6 +112,10 @@ void normalise_rows(double* R, int64_t per, int nb, double* logs, hipStream_t st
 // q of the current column for every parent against right environments Rc
 // (parent b reads row rid[b] of Rc; column geometry cc; T must be in place).
 void q_against(tnb_beam* bm, const BCol& cc, const double* Rc, const int32_t* rid, double* q, hipStream_t st);
+// Droplet bookkeeping of the step that fixed cluster n (droplets.hip): the
+// kept branches sel[0 .. nsel) of the merge, with the scores of every
+// candidate and (merge) the parents' boundary classes; writes the *n buffers.
+void droplet_step(tnb_beam* bm, int n, uint32_t Un, bool merge, int nb, int nsel, hipStream_t st);
 // Eq. (1) for K states [K][N] of +-1 (clusters.hip): edges in order, then fields, no FMA.
 __global__ void ising_energy_kernel(const int8_t* __restrict__ s, int64_t K, int N, int E,
                                     const int* __restrict__ ei, const int* __restrict__ ej,

@@ -924,6 +924,7 @@ extern "C" tnb_status tnb_branch_step(tnb_beam* bm, double* p_disc_log, tnb_stre
     }
     hipLaunchKernelGGL(new_beam_kernel, dim3(nsel), dim3(64), 0, st, bm->win.p, nsel, bm->X.p, bm->ncell, n, bm->rid.p,
                        bm->Xn.p, bm->logpn.p, bm->ridn.p);
+    if (bm->dopt.max_droplets > 0) droplet_step(bm, n, Un, !last, nb, nsel, st);
     // left vectors over the bond right of Psi site 2c
     const Mps& psi = bm->env->psi[r + 1];
     const Site& A2c = psi.sites[2 * c];
@@ -935,6 +936,14 @@ extern "C" tnb_status tnb_branch_step(tnb_beam* bm, double* p_disc_log, tnb_stre
     std::swap(bm->logp, bm->logpn);
     std::swap(bm->rid, bm->ridn);
     std::swap(bm->L, bm->Ln);
+    if (bm->dopt.max_droplets > 0) {
+      std::swap(bm->Ep, bm->Epn);
+      std::swap(bm->dcnt, bm->dcntn);
+      std::swap(bm->dlen, bm->dlenn);
+      std::swap(bm->dEv, bm->dEvn);
+      std::swap(bm->dcell, bm->dcelln);
+      std::swap(bm->dmask, bm->dmaskn);
+    }
     bm->Ld = A2c.dr;
     bm->npar = nsel;
     bm->step = n + 1;

@@ -148,8 +148,8 @@ struct Lattice {
 
 Lattice validate_instance(const tnb_instance* inst);
 
-// A device double holding 1.0 for the current device (allocated once per
-// device and kept for the life of the process).
+// A device weight of 1 for the current device (a constant of the code
+// object, looked up once per device).
 const double* unit_weight();
 const float* unit_weight32();
 
