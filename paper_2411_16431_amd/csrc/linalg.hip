@@ -654,9 +654,7 @@ static void small_svd(const double* M, int64_t n, int m, int t, double cut, doub
   if (shm > 65536)
     HIPC(hipFuncSetAttribute(reinterpret_cast<const void*>(small_svd_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm)));
-  // one wave for small blocks: the rounds' barriers then cost next to nothing
-  const unsigned threads = int64_t(n) * m <= 4096 ? 64u : 256u;
-  hipLaunchKernelGGL(small_svd_kernel, dim3(1), dim3(threads), shm, st, M, int(n), m, t, cut, U, S, VT);
+  hipLaunchKernelGGL(small_svd_kernel, dim3(1), dim3(256), shm, st, M, int(n), m, t, cut, U, S, VT);
   HIPC(hipGetLastError());
 }
 
