@@ -292,13 +292,18 @@ def diagram_apply(clusters, r, k, mode, A, K, X, prec="f64"):
     return out
 
 
-def solve(inst, beta, chi, M, K=8, **env_kw):
+def solve(inst, beta, chi, M, K=8, droplets=None, **env_kw):
     """Whole pipeline on the device: clusters, boundary MPSs, every beam step,
-    export of the final candidates and their energies; returns the K lowest."""
+    export of the final candidates and their energies; returns the K lowest.
+    droplets: keyword arguments of Beam.enable_droplets; the excitations of
+    the branch that holds the lowest energy are then returned as
+    "droplet_states" / "droplet_dE" (Fig. 4)."""
     import torch
     cl = Clusters(inst, beta)
     env = Env(cl, EnvOptions(chi=chi, **env_kw))
     beam = Beam(env, M)
+    if droplets is not None:
+        beam.enable_droplets(**droplets)
     n_steps = inst.R * inst.C
     pd = -math.inf
     marg = 0
@@ -307,8 +312,15 @@ def solve(inst, beta, chi, M, K=8, **env_kw):
         marg += npar * int(round(math.log2(d)))
         pd = beam.step()
     states, E = beam.lowest(K, inst.n_spins)
-    return dict(states=states.cpu().numpy(), energies=E.cpu().numpy(), logZ=env.logZ, p_d_log=pd, env=env,
-                beam=beam, spin_marginals=marg)
+    out = dict(states=states.cpu().numpy(), energies=E.cpu().numpy(), logZ=env.logZ, p_d_log=pd, env=env,
+               beam=beam, spin_marginals=marg)
+    if droplets is not None:
+        npar = beam.info()[1]
+        fin, _ = beam.export(npar, inst.n_spins)
+        best = int(torch.argmin(energies(inst, fin)).item())   # first branch of lowest energy
+        ds, dE = beam.droplets(best, inst.n_spins, droplets.get("max_droplets", 16))
+        out["droplet_states"], out["droplet_dE"] = ds.cpu().numpy(), dE.cpu().numpy()
+    return out
 
 
 _ALLOC_KEEP = []

@@ -110,3 +110,18 @@ def test_droplet_limits_and_order_of_calls():
     beam.step()
     with pytest.raises(pk.TnbError):
         beam.enable_droplets()                  # after the first step
+
+
+def test_solve_returns_the_best_branch_droplets_planted():
+    # planted king's lattice: the exact ground energy E0 bounds every
+    # excitation state from below, and each state costs E_best + dE
+    pk, torch = _gpu()
+    from tnb_inputs import planted_king
+    inst, s_star, E0 = planted_king(6, 6, 1, 11)
+    res = pk.solve(inst, 3.0, 16, 32, K=2, droplets=dict(max_droplets=12, max_losers=6, max_cells=16))
+    assert res["energies"][0] == E0
+    ds, dE = res["droplet_states"], res["droplet_dE"]
+    assert len(ds) > 0 and np.all(np.diff(dE) >= 0)
+    E = ising.energies(inst, ds)
+    np.testing.assert_array_equal(E - res["energies"][0], dE)
+    assert np.all(E >= E0)
