@@ -16,4 +16,6 @@ Modules
              boundary MPS and branch and bound with boundary merging.
   droplets -- Sec. III.A, Fig. 4: excitations above each main branch from
              the members its merge discards.
+  lbp     -- Sec. IV, Fig. 9: loopy belief propagation on projected cluster
+             states and the reduction to the most probable states.
 """

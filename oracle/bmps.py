@@ -159,7 +159,9 @@ class Network:
     """Boltzmann tables of one instance at inverse temperature beta (Eq. 6),
     each shifted by its minimum energy; `shift` is the total log-scale."""
 
-    def __init__(self, inst, beta):
+    def __init__(self, inst, beta, keep=None):
+        """keep: optional boolean mask per cluster (the states a local
+        dimensional reduction retains, Sec. IV); the others get weight 0."""
         self.P = P = Potts(inst)
         self.beta = beta
         self.R, self.C = P.R, P.C
@@ -169,7 +171,8 @@ class Network:
             E = P.local_energy(n)
             Emin = E.min()
             shift += -beta * Emin
-            self.w.append(np.exp(-beta * (E - Emin)))
+            w = np.exp(-beta * (E - Emin))
+            self.w.append(w if keep is None else np.where(keep[n], w, 0.0))
         self.W = {}
         for (m, n) in P.inter:
             Eb = P.bond_energy(m, n)
@@ -603,9 +606,10 @@ class Env:
         self.psi, self.lam, self.logZ, self.net = psi, lam, logZ, net
 
 
-def contract_env(inst, beta, opts):
-    """All boundary MPSs, bottom-up, and log Z (Eq. 10) from the top row."""
-    net = Network(inst, beta)
+def contract_env(inst, beta, opts, keep=None):
+    """All boundary MPSs, bottom-up, and log Z (Eq. 10) from the top row
+    (keep: the retained states of a local dimensional reduction, Sec. IV)."""
+    net = Network(inst, beta, keep)
     R = net.R
     psi = {R: trivial_mps(net.phys_dims(R)[0])}
     lam = {R: 0.0}
