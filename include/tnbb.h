@@ -326,6 +326,28 @@ typedef struct {
 } tnb_allocator;
 tnb_status tnb_set_allocator(const tnb_allocator* a);
 
+/* Loopy belief propagation over the cluster graph (Sec. IV, Fig. 9), with
+ * messages on projected cluster states (Eq. 4): every directed bond m -> n
+ * carries nu[m->n](P^{nm} x_n), uniform at the start; one iteration forms
+ * mu[m->n](xbar_m) = sum over x_m with P^{mn} x_m = xbar_m of the local weight
+ * times the messages into m from its other neighbours, then
+ * nu[m->n](xbar_n) = sum_xbar_m W_mn(xbar_m, xbar_n) mu[m->n](xbar_m),
+ * normalised to sum 1, for every bond at once.  After `iters` iterations the
+ * beliefs p_n(x) ~ w_n(x) prod_m nu[m->n](P^{nm} x), normalised per cluster,
+ * are written to d_p (device, FP64): cluster n's 2^{k_n} values at offset
+ * sum_{n' < n} 2^{k_n'}; p_len is d_p's capacity.  *max_change (may be NULL)
+ * receives the largest change of a message in the last iteration.
+ * Errors: TNB_EINVAL (handle, iters outside [0, 100000], d_p too short). */
+tnb_status tnb_lbp_marginals(const tnb_clusters* cl, int32_t iters, double* d_p, int64_t p_len,
+                             double* max_change, tnb_stream stream);
+
+/* Local dimensional reduction (Sec. IV): keep the `keep` states of largest
+ * belief (after `iters` iterations; ties: the smaller x) in every cluster and
+ * give the others weight 0, so that every later tnb_contract_env and search
+ * on this handle works on the reduced state space.  Call before building
+ * environments.  Errors: TNB_EINVAL (handle, keep < 1, iters). */
+tnb_status tnb_reduce_clusters(tnb_clusters* cl, int32_t keep, int32_t iters, tnb_stream stream);
+
 /* Excitations above each branch from the boundary merge (Sec. III.A, Fig. 4).
  * When tnb_branch_step groups candidates by their boundary, the group's most
  * probable member is kept and every other member differs from it only away

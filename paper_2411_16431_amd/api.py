@@ -93,6 +93,23 @@ class Clusters(_Handle):
         _check(L.lib().tnb_build_clusters(ctypes.byref(hi.c), float(beta), _stream(), ctypes.byref(h)))
         self._h = h
 
+    def lbp_marginals(self, iters):
+        """tnb_lbp_marginals: (list of per-cluster belief tensors, largest
+        message change of the last iteration)."""
+        import torch
+        ks = np.bincount(np.asarray(self.inst.cell_of), minlength=self.inst.R * self.inst.C)
+        sizes = [1 << int(k) for k in ks]
+        p = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+        ch = ctypes.c_double()
+        _check(L.lib().tnb_lbp_marginals(self._h, int(iters), ctypes.c_void_p(p.data_ptr()), p.numel(),
+                                         ctypes.byref(ch), _stream()))
+        return list(torch.split(p, sizes)), ch.value
+
+    def reduce(self, keep, iters):
+        """tnb_reduce_clusters: keep the `keep` most probable states of every
+        cluster by LBP beliefs; the others get weight 0 (Sec. IV)."""
+        _check(L.lib().tnb_reduce_clusters(self._h, int(keep), int(iters), _stream()))
+
     def local_energy(self, n):
         import torch
         k = int(np.sum(np.asarray(self.inst.cell_of) == n))

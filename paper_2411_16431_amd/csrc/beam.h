@@ -13,6 +13,23 @@ struct Cand {
 
 inline unsigned nblk(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+// Ascending sort of npow2 candidates (a power of two) by (gkey, skey, b, x).
+void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st);
+__host__ __device__ inline uint64_t score_key(double v) {
+  uint64_t u;
+  memcpy(&u, &v, sizeof(u));
+  uint64_t asc = (u >> 63) ? ~u : (u | (1ull << 63));  // ascending in v
+  return ~asc;                                          // ascending in -v
+}
+__host__ __device__ inline double key_score(uint64_t k) {
+  uint64_t asc = ~k;
+  uint64_t u = (asc >> 63) ? (asc & ~(1ull << 63)) : ~asc;
+  double v;
+  memcpy(&v, &u, sizeof(v));
+  return v;
+}
+
+
 // ---- per-column geometry of the beam's row ----------------------------------
 struct UpNb {
   uint32_t Bup_in_up = 0;  // spins of the upper cell facing n

@@ -25,20 +25,6 @@
 namespace tnb {
 
 
-__host__ __device__ inline uint64_t score_key(double v) {
-  uint64_t u;
-  memcpy(&u, &v, sizeof(u));
-  uint64_t asc = (u >> 63) ? ~u : (u | (1ull << 63));  // ascending in v
-  return ~asc;                                          // ascending in -v
-}
-__host__ __device__ inline double key_score(uint64_t k) {
-  uint64_t asc = ~k;
-  uint64_t u = (asc >> 63) ? (asc & ~(1ull << 63)) : ~asc;
-  double v;
-  memcpy(&v, &u, sizeof(v));
-  return v;
-}
-
 __device__ inline bool cand_less(const Cand& a, const Cand& b) {
   if (a.gkey != b.gkey) return a.gkey < b.gkey;
   if (a.skey != b.skey) return a.skey < b.skey;
@@ -93,7 +79,7 @@ __global__ void __launch_bounds__(1024) bitonic_local(Cand* __restrict__ a, int6
   (void)n;
 }
 
-static void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st) {
+void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st) {
   int lg = 0;
   while ((int64_t(1) << lg) < npow2) ++lg;
   KTimer _t("sort", st, 0.0, 2.0 * sizeof(Cand) * double(npow2) * lg * (lg + 1) / 2);

@@ -1,0 +1,97 @@
+"""Loopy belief propagation and the local dimensional reduction (Sec. IV,
+Fig. 9) on the GPU against the oracle: beliefs after 0..12 iterations
+(<= 1e-12), exactness on a cluster tree, the retained states and log Z of the
+reduced network, the reduced search, and the benchmark's 2^16-state
+clusters."""
+import numpy as np
+import pytest
+
+from tnb_inputs import make_instance
+from oracle.lbp import lbp, select, exact_marginals
+from oracle.bmps import contract_env, Options
+from oracle.potts import Potts
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_16431_amd as pk
+    return pk, torch
+
+
+def _close(got, ref, tol=1e-12):
+    for g, r in zip(got, ref):
+        g = g.cpu().numpy()
+        assert np.abs(g - r).max() <= tol * r.max()
+
+
+@pytest.mark.parametrize("kind,kw,beta", [("king", dict(R=3, C=3, a=2), 1.0), ("zephyr", dict(m=1, t=2), 0.7),
+                                          ("zephyr", dict(m=2, t=2), 0.5)])
+def test_beliefs_match_oracle(kind, kw, beta):
+    pk, torch = _gpu()
+    inst = make_instance(kind, 17, jdist="uniform", hdist="uniform0.1", **kw)
+    cl = pk.Clusters(inst, beta)
+    for it in (0, 1, 4, 12):
+        got, ch = cl.lbp_marginals(it)
+        ref, _, rch = lbp(inst, beta, it)
+        _close(got, ref)
+        assert abs(ch - rch) <= 1e-12
+
+
+def test_beliefs_exact_on_a_cluster_tree():
+    pk, torch = _gpu()
+    inst = make_instance("king", 23, jdist="uniform", hdist="uniform0.1", R=1, C=5, a=2)
+    cl = pk.Clusters(inst, 0.9)
+    got, ch = cl.lbp_marginals(15)
+    _close(got, exact_marginals(inst, 0.9, Potts(inst)))
+    assert ch <= 1e-14
+
+
+def test_reduction_matches_oracle_and_restricts_the_search():
+    pk, torch = _gpu()
+    inst = make_instance("zephyr", 29, jdist="uniform", hdist="uniform0.1", m=2, t=2)
+    beta, keep, iters = 0.8, 12, 6
+    ref_bel, _, _ = lbp(inst, beta, iters)
+    # the retained sets are unique where the keep-th and next beliefs differ
+    for p in ref_bel:
+        s = np.sort(p)[::-1]
+        if len(s) > keep:
+            assert s[keep - 1] - s[keep] > 1e-9 * s[0]
+    masks = select(ref_bel, keep)
+    cl = pk.Clusters(inst, beta)
+    cl.reduce(keep, iters)
+    env = pk.Env(cl, pk.EnvOptions(chi=64))
+    ref = contract_env(inst, beta, Options(chi=64), keep=masks).logZ
+    assert abs(env.logZ - ref) <= 1e-12 * abs(ref)
+    beam = pk.Beam(env, 16)
+    for _ in range(inst.R * inst.C):
+        beam.step()
+    states, E = beam.lowest(4, inst.n_spins)
+    X = Potts(inst).cluster_of_states(states.cpu().numpy())
+    for x in X:
+        assert all(masks[n][x[n]] for n in range(len(masks)))
+
+
+def test_benchmark_size_clusters():
+    # Zephyr Z_2 t=4: 2^16 states per cluster, messages on 2^8 projections
+    pk, torch = _gpu()
+    inst = make_instance("zephyr", 1000, jdist="uniform", hdist="uniform0.1", m=2, t=4)
+    cl = pk.Clusters(inst, 1.0)
+    got, _ = cl.lbp_marginals(2)
+    ref, _, _ = lbp(inst, 1.0, 2)
+    _close(got, ref)
+    for g in got:
+        assert abs(float(g.sum()) - 1.0) <= 1e-12
+
+
+def test_reduction_arguments():
+    pk, torch = _gpu()
+    inst = make_instance("king", 3, jdist="uniform", hdist="zero", R=2, C=2, a=1)
+    cl = pk.Clusters(inst, 1.0)
+    for keep, it in ((0, 3), (2, -1), (2, 100001)):
+        with pytest.raises(pk.TnbError) as e:
+            cl.reduce(keep, it)
+        assert e.value.code == -1
