@@ -1743,7 +1743,7 @@ struct Zipper {
     return out_gemm_ok(md, f) && f.nHR <= 32 && f.nHR * f.nHL <= 4096;
   }
   void y2_gemm(const RowGeom::Med& md, const MedF& f, const double* Kc, const double* X2, int Dg, int Db, int s,
-               double* Y2, const char* timer, int tag) {
+               double* Y2, const char* timer, int tag, const char* wtimer = "medf_Y2w") {
     const Split sp = make_split(pext_host(f.hL_pos, md.pos_d_ell), md.dld);
     const int blk = Db * Dg;
     const int64_t nK = int64_t(md.dL) * blk, xblk = int64_t(md.drd) * Dg * s;
@@ -1765,7 +1765,7 @@ struct Zipper {
     la::gemm_mfma(sp.nh, M, N, Kd, a, b, Sg.p, la::Ix{uint32_t(Db), int64_t(md.drd) * Db * s, s},
                   la::Ix{uint32_t(s), int64_t(Db) * s, 1}, int64_t(md.db2) * md.drd * Db * s, 1.0, 0.0, st, timer,
                   tag);
-    wsum<0>(md, f, Db * s, Y2);
+    wsum<0>(md, f, Db * s, Y2, wtimer);
   }
   // W2 [rd][b'][hL][b][j] from the site A [a' + da2 b'][a][b] and Y [rho][a][j]:
   //   S[h][b'][rd][b][j] = sum_{r, a} A[a'(h, r) + da2 b'][a][b] Y[rho(rd, a'(h, r))][a][j]
@@ -1794,13 +1794,13 @@ struct Zipper {
     la::gemm_mfma(sp.nh, M, N, Kd, a, b, Sg.p, la::Ix{uint32_t(Db), int64_t(md.drd) * Db * s, s},
                   la::Ix{uint32_t(s), int64_t(Db) * s, 1}, int64_t(md.db2) * md.drd * Db * s, 1.0, 0.0, st, "medf_W2g",
                   4);
-    wsum<1>(md, f, Db * s, W2);
+    wsum<1>(md, f, Db * s, W2, "medf_W2w");
   }
   template <int MODE>
-  void wsum(const RowGeom::Med& md, const MedF& f, int blk, double* out) {
+  void wsum(const RowGeom::Med& md, const MedF& f, int blk, double* out, const char* timer) {
     const int nO = MODE == 0 ? f.nHR : f.nHL, nh = MODE == 0 ? f.nHL : f.nHR;
     const double pairs = double(md.drd) * md.db2;
-    KTimer _t(MODE == 0 ? "medf_Y2w" : "medf_W2w", st, pairs * 2.0 * nO * nh * blk, pairs * 8.0 * double(nO + nh) * blk);
+    KTimer _t(timer, st, pairs * 2.0 * nO * nh * blk, pairs * 8.0 * double(nO + nh) * blk);
     hipLaunchKernelGGL(medf_wsum_kernel<MODE>, dim3(unsigned(md.drd * md.db2)), dim3(256), 0, st, f, Sg.p, blk, out);
     HIPC(hipGetLastError());
   }
@@ -2161,9 +2161,13 @@ struct Zipper {
       make_medf(mirror_med(g.med[(k - 1) / 2]), &f);
       const auto& mm = f.md;  // mirrored: "rho" is l, "l" is rho
       T* YfT = tb<T>(Yf, size_t(mm.drd) * mm.db2 * f.nHR * Da * s);
-      const T* QT = in_T<T>(Q, int64_t(mm.drd) * mm.dld * t * s, cX);
       const int nj = (s + 15) / 16;
-      {
+      if (sizeof(T) == sizeof(double) && y2_gemm_ok(mm, f)) {
+        // the grouped product of the apply on the mirrored geometry: L as
+        // stored ([rho][a][t]) is its connector, P2 its X2
+        y2_gemm(mm, f, Lin, Q, t, Da, s, reinterpret_cast<double*>(YfT), "medf_lbing", 5, "medf_lbinw");
+      } else {
+        const T* QT = in_T<T>(Q, int64_t(mm.drd) * mm.dld * t * s, cX);
         KTimer _t1(TNB_TN("medf_lbin"), st, double(mm.drd) * mm.dL * (2.0 * Da * t * s + 2.0 * f.nHR * Da * s),
                    sz * (double(mm.dL) * Da * t + double(mm.dld) * mm.drd * t * s +
                          double(mm.drd) * mm.db2 * f.nHR * Da * s));

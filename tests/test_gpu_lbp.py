@@ -52,7 +52,8 @@ def test_beliefs_exact_on_a_cluster_tree():
 
 def test_reduction_matches_oracle_and_restricts_the_search():
     pk, torch = _gpu()
-    inst = make_instance("zephyr", 29, jdist="uniform", hdist="uniform0.1", m=2, t=2)
+    # Zephyr Z_1 t=2 (8-spin clusters), small enough for the oracle's exact contraction
+    inst = make_instance("zephyr", 29, jdist="uniform", hdist="uniform0.1", m=1, t=2)
     beta, keep, iters = 0.8, 12, 6
     ref_bel, _, _ = lbp(inst, beta, iters)
     # the retained sets are unique where the keep-th and next beliefs differ
