@@ -59,7 +59,6 @@ namespace la {
 struct Ix {
   uint32_t n0 = 0;
   int64_t s1 = 0, s0 = 0;
-  int32_t sh = -1;  // log2(n0) when n0 is a power of two (set by gemm_mfma)
 };
 struct Operand {
   const double* p = nullptr;

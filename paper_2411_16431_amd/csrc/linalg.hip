@@ -740,28 +740,20 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int GK = 16;
 
 __device__ __forceinline__ int64_t ix_off(uint32_t i, const Ix& x) {
-  if (!x.n0) return int64_t(i) * x.s0;
-  if (x.sh >= 0) return int64_t(i >> x.sh) * x.s1 + int64_t(i & (x.n0 - 1u)) * x.s0;
-  return int64_t(i / x.n0) * x.s1 + int64_t(i % x.n0) * x.s0;
-}
-
-static Ix with_shift(Ix x) {
-  x.sh = -1;
-  if (x.n0 && (x.n0 & (x.n0 - 1u)) == 0) x.sh = __builtin_ctz(x.n0);
-  return x;
+  return x.n0 ? int64_t(i / x.n0) * x.s1 + int64_t(i % x.n0) * x.s0 : int64_t(i) * x.s0;
 }
 
 // TAG only names the instance (one per use in the mediating diagram, 0 for
 // the rest), so that kernel traces tell the uses apart.
 template <int TAG, int BM, int BN>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN <= 4 ? 4 : 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN <= 8 ? 3 : 2)))
 gemm_mfma_kernel(int M, int N, int K, Operand A, Operand B, double* __restrict__ C, Ix cr, Ix cc, int64_t cbs,
                  double alpha, double beta, int a_kfast, int b_kfast, int tiles_n) {
   constexpr int TM = 32 * BM, TN = 32 * BN;          // the workgroup's tile
   constexpr int NA = TM * GK / 256, NB = TN * GK / 256;  // staged elements per thread
   constexpr int SA = 256 / TM, SB = 256 / TN;         // k rows per pass when staging along m / n
-  __shared__ double As[2][GK][TM + 1];
-  __shared__ double Bs[2][GK][TN + 1];
+  __shared__ double As[GK][TM + 1];
+  __shared__ double Bs[GK][TN + 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int tm0 = int(blockIdx.x / tiles_n) * TM, tn0 = int(blockIdx.x % tiles_n) * TN;
@@ -828,16 +820,16 @@ gemm_mfma_kernel(int M, int N, int K, Operand A, Operand B, double* __restrict__
       }
     }
   };
-  auto store = [&](int q) {
+  auto store = [&]() {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      if (a_kfast) As[q][t % GK][t / GK + 16 * i] = ra[i];
-      else As[q][t / TM + SA * i][t % TM] = ra[i];
+      if (a_kfast) As[t % GK][t / GK + 16 * i] = ra[i];
+      else As[t / TM + SA * i][t % TM] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      if (b_kfast) Bs[q][t % GK][t / GK + 16 * i] = rb[i];
-      else Bs[q][t / TN + SB * i][t % TN] = rb[i];
+      if (b_kfast) Bs[t % GK][t / GK + 16 * i] = rb[i];
+      else Bs[t / TN + SB * i][t % TN] = rb[i];
     }
   };
   v4d acc[BM][BN];
@@ -846,28 +838,24 @@ gemm_mfma_kernel(int M, int N, int K, Operand A, Operand B, double* __restrict__
 #pragma unroll
     for (int j = 0; j < BN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
   const int li = lane & 15, lk = lane >> 4;
-  // double-buffered slices: the next slice goes from registers into the other
-  // buffer while this one is read, so one barrier per slice suffices
   load(0);
-  store(0);
-  __syncthreads();
-  for (int k0 = 0, q = 0; k0 < K; k0 += GK, q ^= 1) {
-    const bool more = k0 + GK < K;
-    if (more) load(k0 + GK);
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + GK < K) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       double a[BM], bv[BN];
 #pragma unroll
-      for (int i = 0; i < BM; ++i) a[i] = As[q][kk + lk][wm * 16 * BM + i * 16 + li];
+      for (int i = 0; i < BM; ++i) a[i] = As[kk + lk][wm * 16 * BM + i * 16 + li];
 #pragma unroll
-      for (int j = 0; j < BN; ++j) bv[j] = Bs[q][kk + lk][wn * 16 * BN + j * 16 + li];
+      for (int j = 0; j < BN; ++j) bv[j] = Bs[kk + lk][wn * 16 * BN + j * 16 + li];
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
         for (int j = 0; j < BN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    if (more) store(q ^ 1);
-    __syncthreads();
   }
   double* Cb = C + b * cbs;
 #pragma unroll
@@ -919,18 +907,11 @@ void gemm_mfma(int batch, int M, int N, int K, const Operand& A, const Operand& 
   KTimer _t(timer, s, 2.0 * M * double(N) * double(K) * batch,
             8.0 * (double(M) * K + double(K) * N + double(M) * N) * batch);
   const int akf = kfast(A.c, A.r) ? 1 : 0, bkf = kfast(B.r, B.c) ? 1 : 0;
-  Operand As_ = A, Bs_ = B;
-  As_.r = with_shift(A.r);
-  As_.c = with_shift(A.c);
-  Bs_.r = with_shift(B.r);
-  Bs_.c = with_shift(B.c);
-  cr = with_shift(cr);
-  cc = with_shift(cc);
   auto run = [&](int v) {
     const int64_t tiles = int64_t((M + TMv[v] - 1) / TMv[v]) * ((N + TNv[v] - 1) / TNv[v]);
     for (int b0 = 0; b0 < batch; b0 += 65535) {
       const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
-      Operand a = As_, bb = Bs_;
+      Operand a = A, bb = B;
       a.p += A.bs * b0;
       bb.p += B.bs * b0;
       const dim3 grid{unsigned(tiles), unsigned(nb), 1u};
