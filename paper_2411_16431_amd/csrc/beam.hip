@@ -79,14 +79,35 @@ __global__ void __launch_bounds__(1024) bitonic_local(Cand* __restrict__ a, int6
   (void)n;
 }
 
+// A whole sort of n <= kChunk elements (a power of two) in one workgroup:
+// the network of bitonic_step, stage after stage, on an LDS copy.
+__global__ void __launch_bounds__(1024) bitonic_small(Cand* __restrict__ a, int n) {
+  __shared__ Cand sh[kChunk];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sh[i] = a[i];
+  __syncthreads();
+  for (int k = 2; k <= n; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+        const int i = 2 * j * (t / j) + (t % j);
+        const int l = i + j;
+        const bool up = (i & k) == 0;
+        const Cand x = sh[i], y = sh[l];
+        if (up ? cand_less(y, x) : cand_less(x, y)) {
+          sh[i] = y;
+          sh[l] = x;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = sh[i];
+}
+
 void bitonic_sort(Cand* a, int64_t npow2, hipStream_t st) {
   int lg = 0;
   while ((int64_t(1) << lg) < npow2) ++lg;
   KTimer _t("sort", st, 0.0, 2.0 * sizeof(Cand) * double(npow2) * lg * (lg + 1) / 2);
-  if (npow2 < kChunk) {
-    for (int64_t k = 2; k <= npow2; k <<= 1)
-      for (int64_t j = k >> 1; j > 0; j >>= 1)
-        hipLaunchKernelGGL(bitonic_step, dim3(nblk(npow2)), dim3(256), 0, st, a, npow2, j, k);
+  if (npow2 <= kChunk) {
+    if (npow2 > 1) hipLaunchKernelGGL(bitonic_small, dim3(1), dim3(1024), 0, st, a, int(npow2));
     HIPC(hipGetLastError());
     return;
   }
