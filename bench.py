@@ -399,7 +399,7 @@ def main():
                    "power_iters": args.power_iters},
         "best_energy": best, "energy_gap_vs_oracle": gap_oracle, "energy_gap_exact": exact,
         "energy_gap_planted": planted,
-        "logZ": res["logZ"], "spin_marginals_per_step": marg,
+        "logZ": res["logZ"], "logZ_sign": res["env"].sign, "spin_marginals_per_step": marg,
         "roofline": roof, "cpu_baseline": cpu, "adjoint": adj, "fp32": f32,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
         "kernels": kernel_table(prof, args.steps),

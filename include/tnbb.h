@@ -139,8 +139,12 @@ typedef struct {
  * matrix-free randomized SVD and followed by a one-site variational update
  * of the two sites next to the zipper centre (var_window); then var_sweeps
  * full one-site variational sweeps at 2*chi that maximise the overlap with
- * T_r Psi_{r+1}; then a left-to-right SVD sweep to chi.  log_z (host, may be NULL) receives log Z.  The returned
- * handle keeps a reference to `cl`, which must outlive it.
+ * T_r Psi_{r+1}; then a left-to-right SVD sweep to chi.  log_z (host, may
+ * be NULL) receives log |Z|: a truncated environment need not stay positive,
+ * and the sign of the approximate Z is reported by tnb_env_logz (the
+ * conditional marginals, a ratio of two contractions of the same network,
+ * take the sign of their sum and are unaffected).  The returned handle
+ * keeps a reference to `cl`, which must outlive it.
  * Errors: TNB_EINVAL (options), TNB_ENUMERIC (zero or non-finite
  * contraction), TNB_ENOMEM. */
 tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opts, tnb_stream stream,
@@ -177,6 +181,11 @@ tnb_status tnb_diagram_apply(const tnb_clusters* cl, int32_t r, int32_t k, int32
                              const double* d_A, int32_t Da, int32_t Db, const double* d_K,
                              int32_t Dg, const double* d_X, int32_t s, double* d_out,
                              int64_t out_len, tnb_stream stream);
+
+/* log |Z| of an environment and the sign (+1 or -1) of the approximate Z
+ * (the top-row contraction); either pointer may be NULL.
+ * Errors: TNB_EINVAL (handle). */
+tnb_status tnb_env_logz(const tnb_env* env, double* log_z, int32_t* sign);
 
 /* Norm-free diagnostic: number of sites of Psi_r and the shape of site k. */
 tnb_status tnb_env_site_shape(const tnb_env* env, int32_t r, int32_t k, int32_t* dl,

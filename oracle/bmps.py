@@ -622,4 +622,6 @@ def contract_env(inst, beta, opts, keep=None):
     for s in top:
         val = val * s.reshape(-1)[0] if s.size == 1 else val * s.sum()
     logZ = net.shift + lam[1] + ln0 + np.log(abs(val))
-    return Env(psi, lam, logZ, net)
+    env = Env(psi, lam, logZ, net)
+    env.sign = 1 if val > 0 else -1     # a truncated environment can be sign-indefinite
+    return env

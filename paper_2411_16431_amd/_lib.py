@@ -55,6 +55,7 @@ SIGNATURES = {
     "tnb_beam_export": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_beam_lowest": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),
     "tnb_beam_droplets_enable": (c_int32, [c_void_p, P(TnbDropletOpts)]),
+    "tnb_env_logz": (c_int32, [c_void_p, P(ctypes.c_double), P(c_int32)]),
     "tnb_lbp_marginals": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.c_int64, P(ctypes.c_double), c_void_p]),
     "tnb_reduce_clusters": (c_int32, [c_void_p, c_int32, c_int32, c_void_p]),
     "tnb_beam_droplets": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, P(c_int32), c_void_p]),

@@ -161,6 +161,9 @@ class Env(_Handle):
                                         ctypes.byref(lz)))
         self._h = h
         self.logZ = lz.value
+        sg = ctypes.c_int32()
+        _check(L.lib().tnb_env_logz(self._h, None, ctypes.byref(sg)))
+        self.sign = sg.value   # sign of the approximate Z (log Z is log |Z|)
 
     def site_shape(self, r, k):
         a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -60,5 +60,6 @@ struct tnb_env {
   tnb_env_opts opts{};
   std::vector<tnb::Mps> psi;  // psi[r], r = 1..R (psi[0] unused)
   double logZ = 0.0;
+  int zsign = 1;  // sign of the approximate Z (top-row contraction)
   tnb::la::Scratch ws;
 };

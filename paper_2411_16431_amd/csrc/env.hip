@@ -2560,9 +2560,18 @@ extern "C" tnb_status tnb_contract_env(tnb_clusters* cl, const tnb_env_opts* opt
       std::fprintf(stderr, "[tnb] top contraction value %.6e (sign %+d), ln0 %.6f, lam1 %.6f\n", val,
                    val > 0 ? 1 : -1, ln0, env->psi[1].logscale);
     env->logZ = cl->shift + env->psi[1].logscale + ln0 + std::log(std::fabs(val));
+    env->zsign = val > 0.0 ? 1 : -1;
     if (log_z) *log_z = env->logZ;
     HIPC(hipStreamSynchronize(st));
     *out = env.release();
+  });
+}
+
+extern "C" tnb_status tnb_env_logz(const tnb_env* env, double* log_z, int32_t* sign) {
+  return guarded([&] {
+    if (!env || env->kind != KIND_ENV) fail(TNB_EINVAL, "not an env handle");
+    if (log_z) *log_z = env->logZ;
+    if (sign) *sign = env->zsign;
   });
 }
 

@@ -99,3 +99,22 @@ def test_invalid_options_rejected():
     with pytest.raises(pk.TnbError) as e:
         pk.Env(cl, pk.EnvOptions(chi=0))
     assert e.value.code == -1
+
+
+def test_sign_of_a_sign_indefinite_truncation_is_reported():
+    # chi = 2 without variational sweeps at beta = 3 leaves this king's
+    # lattice with a negative approximate Z; log Z is log |Z| on both sides
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_16431_amd as pk
+    from tnb_inputs import make_instance
+    from oracle.bmps import contract_env, Options
+    inst = make_instance("king", 67, jdist="uniform", hdist="zero", R=4, C=4, a=2)
+    ref = contract_env(inst, 3.0, Options(chi=2, power=2, var_window=0, var_sweeps=0))
+    cl = pk.Clusters(inst, 3.0)
+    env = pk.Env(cl, pk.EnvOptions(chi=2, var_window=0, var_sweeps=0))
+    assert ref.sign == -1 and env.sign == -1
+    assert abs(env.logZ - ref.logZ) <= 1e-10 * abs(ref.logZ)
+    exact = pk.Env(cl, pk.EnvOptions(chi=64))
+    assert exact.sign == 1
