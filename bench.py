@@ -160,17 +160,41 @@ def parse():
                     help="launch-variant table used when not measuring (default: the committed MI355X table)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: turn two rocprofv3 counter files of the dominant kernel into profiles/*_traffic.json")
-    ap.add_argument("--traffic-kernel", default="medf_Y2")
+    ap.add_argument("--traffic-kernel", default="medf_G2g")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also solve this many instances of the workload (seeds seed..seed+n-1) at once with "
+                         "solve_batch, after the timed region, and report their aggregate rate")
     return ap.parse_args()
 
 
-def make(wl):
+def make(wl, seed=None):
     """The workload's instance, and its exact ground energy when planted (else None)."""
     from tnb_inputs import make_instance, planted_king
+    seed = wl["seed"] if seed is None else seed
     if wl["kind"] == "king_planted":
-        inst, _, E0 = planted_king(wl["kw"]["R"], wl["kw"]["C"], wl["kw"]["a"], wl["seed"], loops_per_cell=1)
+        inst, _, E0 = planted_king(wl["kw"]["R"], wl["kw"]["C"], wl["kw"]["a"], seed, loops_per_cell=1)
         return inst, E0
-    return make_instance(wl["kind"], wl["seed"], jdist=wl["jdist"], hdist=wl["hdist"], **wl["kw"]), None
+    return make_instance(wl["kind"], seed, jdist=wl["jdist"], hdist=wl["hdist"], **wl["kw"]), None
+
+
+def batch_rate(pk, torch, wl, env_kw, n):
+    """n instances of the workload solved one by one and then at once
+    (solve_batch, one stream per instance): aggregate spin marginals/s."""
+    insts = [make(wl, wl["seed"] + i)[0] for i in range(n)]
+    kw = dict(chi=wl["chi"], M=wl["M"], K=wl["K"], **env_kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [pk.solve(i, wl["beta"], **kw) for i in insts]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    par = pk.solve_batch(insts, wl["beta"], workers=n, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    marg = sum(r["spin_marginals"] for r in seq)
+    same = all(a["logZ"] == b["logZ"] and (a["energies"] == b["energies"]).all() for a, b in zip(seq, par))
+    return {"instances": n, "one_by_one_s": t1 - t0, "batch_s": t2 - t1,
+            "one_by_one_spin_marginals_per_s": marg / (t1 - t0), "batch_spin_marginals_per_s": marg / (t2 - t1),
+            "speedup": (t1 - t0) / (t2 - t1), "results_identical": bool(same)}
 
 
 def cpu_baseline(inst, wl, counts, marg_per_step, power):
@@ -373,6 +397,7 @@ def main():
               "med": sum(prof.get(nm, (0, 0))[1] for nm in ("med_apply", "med_applyT", "medf_Y2", "medf_W2",
                                                                 "medf_Y2g", "medf_W2g")) / args.steps}
     adj = adjoint_compare(pk, torch, res["env"], wl, inst)
+    batch = batch_rate(pk, torch, wl, env_kw, args.batch) if args.batch > 1 else None
     f32 = None if args.no_f32 else fp32_compare(pk, torch, inst, wl, env_kw, res, args.steps)
     print("fp32 comparison done", file=sys.stderr, flush=True)
     planted = None if (args.no_planted or E0 is not None) else planted_gap(pk, wl, env_kw)
@@ -400,7 +425,7 @@ def main():
         "best_energy": best, "energy_gap_vs_oracle": gap_oracle, "energy_gap_exact": exact,
         "energy_gap_planted": planted,
         "logZ": res["logZ"], "logZ_sign": res["env"].sign, "spin_marginals_per_step": marg,
-        "roofline": roof, "cpu_baseline": cpu, "adjoint": adj, "fp32": f32,
+        "roofline": roof, "cpu_baseline": cpu, "adjoint": adj, "fp32": f32, "batch": batch,
         "kernels_ms_per_step": {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
         "kernels": kernel_table(prof, args.steps),
         "tuning": args.autotune or (args.tuning if args.tuning and os.path.exists(args.tuning) else None),

@@ -8,9 +8,9 @@ loudly if it has not been built.
 from .api import (TnbError, energies, Clusters, Env, Beam, EnvOptions, solve, library_path,
                   exported_symbols, profile_enable, profile_query, profile_names, FirstRowLogZ,
                   first_row_layout, diagram_dims, diagram_apply, select_lowest, solve_transformed,
-                  autotune, use_torch_allocator)
+                  autotune, use_torch_allocator, solve_batch)
 
 __all__ = ["TnbError", "energies", "Clusters", "Env", "Beam", "EnvOptions", "solve",
            "library_path", "exported_symbols", "profile_enable", "profile_query", "profile_names",
            "FirstRowLogZ", "first_row_layout", "diagram_dims", "diagram_apply", "select_lowest",
-           "solve_transformed", "autotune", "use_torch_allocator"]
+           "solve_transformed", "autotune", "use_torch_allocator", "solve_batch"]

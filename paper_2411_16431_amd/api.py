@@ -343,6 +343,28 @@ def solve(inst, beta, chi, M, K=8, droplets=None, **env_kw):
     return out
 
 
+def solve_batch(instances, beta, chi, M, K=8, workers=None, **env_kw):
+    """solve() for several instances at once: each runs on its own host thread
+    and its own stream, so the kernels of different instances (short, launch-
+    bound ones above all) overlap on the device.  Results are those of
+    solve() one by one, in the order of `instances`."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    workers = workers or min(len(instances), 8)
+    dev = torch.cuda.current_device()
+
+    def run(inst):
+        torch.cuda.set_device(dev)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            out = solve(inst, beta, chi, M, K, **env_kw)
+        s.synchronize()
+        return out
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(run, instances))
+
+
 _ALLOC_KEEP = []
 
 

@@ -179,8 +179,12 @@ void dev_free(void* p, const Allocator* owner) {
 
 static bool g_prof = false;
 static std::vector<ProfRec> g_recs;
+static std::mutex g_prof_mu;  // calls on several host threads record concurrently
 bool prof_on() { return g_prof; }
-void prof_push(const ProfRec& r) { g_recs.push_back(r); }
+void prof_push(const ProfRec& r) {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  g_recs.push_back(r);
+}
 
 // A weight of 1 in device memory (the site weight of a cluster's empty side):
 // a constant of the code object, one copy per device.
@@ -491,6 +495,7 @@ extern "C" tnb_status tnb_bond_energies(const tnb_clusters* cl, int32_t m, int32
 
 extern "C" tnb_status tnb_profile_enable(int32_t on) {
   return guarded([&] {
+    std::lock_guard<std::mutex> lock(tnb::g_prof_mu);
     if (on) {
       for (auto& r : tnb::g_recs) {
         (void)hipEventDestroy(r.a);
@@ -506,6 +511,7 @@ extern "C" tnb_status tnb_profile_query(const char* name, double* total_ms, int6
                                         double* flops, double* bytes) {
   return guarded([&] {
     if (!name) fail(TNB_EINVAL, "name is NULL");
+    std::lock_guard<std::mutex> lock(tnb::g_prof_mu);
     double ms = 0.0, fl = 0.0, by = 0.0;
     int64_t n = 0;
     for (auto& r : tnb::g_recs) {
@@ -528,6 +534,7 @@ extern "C" tnb_status tnb_profile_query(const char* name, double* total_ms, int6
 extern "C" tnb_status tnb_profile_names(char* buf, int64_t len) {
   return guarded([&] {
     if (!buf || len < 1) fail(TNB_EINVAL, "bad buffer");
+    std::lock_guard<std::mutex> lock(tnb::g_prof_mu);
     std::string out;
     std::vector<std::string> seen;
     for (auto& r : tnb::g_recs) {
