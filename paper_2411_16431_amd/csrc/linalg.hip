@@ -349,7 +349,15 @@ void eigh(double* G, int s, double* V, double* lam, hipStream_t st) {
   if (lds_fits(s)) {
     const size_t shm = (2560 + 2 * size_t(s) * s) * sizeof(double);
     allow_lds(jacobi_lds_kernel, shm);
-    hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(1024), shm, st, G, s, V, lam);
+    // G stays in place (the kernel works on an LDS copy), so the launch
+    // widths can be timed against each other: 16 or 4 waves
+    auto run = [&](int v) {
+      hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(v == 0 ? 1024 : 256), shm, st, G, s, V, lam);
+      HIPC(hipGetLastError());
+    };
+    char key[64];
+    std::snprintf(key, sizeof key, "eigh s%d", s);
+    autotune_pick(key, s <= 128 ? 2 : 1, run, st);
   } else {
     hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 2560 * sizeof(double), st, G, s, V, lam);
   }
@@ -529,7 +537,14 @@ static void hestenes(double* A, int m, double* U, double* V, double* S, hipStrea
   if (hestenes_lds_bytes(m) <= 163840) {
     const size_t shm = hestenes_lds_bytes(m);
     allow_lds(hestenes_lds_kernel, shm);
-    hipLaunchKernelGGL(hestenes_lds_kernel, dim3(1), dim3(1024), shm, st, A, m, U, V, S);
+    // A stays in place (LDS copy): 16 or 4 waves, timed by the autotuner
+    auto run = [&](int v) {
+      hipLaunchKernelGGL(hestenes_lds_kernel, dim3(1), dim3(v == 0 ? 1024 : 256), shm, st, A, m, U, V, S);
+      HIPC(hipGetLastError());
+    };
+    char key[64];
+    std::snprintf(key, sizeof key, "hestenes m%d", m);
+    autotune_pick(key, m <= 128 ? 2 : 1, run, st);
   } else {
     hipLaunchKernelGGL(hestenes_kernel, dim3(1), dim3(1024), 0, st, A, m, U, V, S);
   }

@@ -107,3 +107,26 @@ def test_every_variant_agrees_at_full_size(tmp_path):
         got = _run_all(pk, torch, cl, r, k, t)
         for mode in range(3):
             assert _rel(got[mode], base[mode]) <= TOL, (v, mode, _rel(got[mode], base[mode]))
+
+
+def test_eigen_and_svd_launch_widths_agree(tmp_path):
+    # the LDS eigensolver and one-sided Jacobi SVD of the Gram path (the
+    # 2^16-state clusters of Zephyr t=4) at 16 and at 4 waves: the same
+    # boundary MPSs up to rounding, on a planted instance whose truncation is
+    # well conditioned
+    import json
+    pk, torch = _gpu()
+    from tnb_inputs import planted_loops
+    inst, _, _ = planted_loops(2, 4, 91, loops_per_cell=2)
+    cl = pk.Clusters(inst, 1.0)
+    base = pk.Env(cl, pk.EnvOptions(chi=16)).logZ
+    path = str(tmp_path / "w.json")
+    pk.autotune(True, path)
+    pk.Env(cl, pk.EnvOptions(chi=16))
+    keys = [k for k in json.load(open(path)) if k.startswith(("eigh", "hestenes"))]
+    assert keys
+    with open(path, "w") as fh:
+        json.dump({k: 1 for k in keys}, fh)
+    pk.autotune(False, path)
+    four = pk.Env(cl, pk.EnvOptions(chi=16)).logZ
+    assert abs(four - base) <= 1e-10 * abs(base)
