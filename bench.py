@@ -59,9 +59,18 @@ ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0, double>", "medf_W2": "medf_bi
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.
-# Valid only for the kernel source they were taken on (hash of its file).
-KERNEL_SRC = os.path.join(ROOT, "paper_2411_16431_amd", "csrc", "env.hip")
+# Valid only for the kernel source they were taken on: one hash over the file
+# with the GEMM body and the file with its operand maps and launches.
+KERNEL_SRC = [os.path.join(ROOT, "paper_2411_16431_amd", "csrc", f) for f in ("gemm_mfma.hip", "env.hip")]
 TUNING_FILE = os.path.join(ROOT, "paper_2411_16431_amd", "tuning_mi355x.json")
+
+
+def source_sha(hashlib):
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, workload):
@@ -69,8 +78,7 @@ def measured_traffic(kernel, workload):
     try:
         with open(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))) as fh:
             rec = json.load(fh)
-        with open(KERNEL_SRC, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        sha = source_sha(hashlib)
     except (OSError, ValueError):
         return None
     if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("source_sha256") != sha:
@@ -128,8 +136,7 @@ def write_traffic(fetch_csv, write_csv, timer, workload, copy_bytes=8 << 27):
         out[key + "_factor"] = factor
         out["launches"] = len(mine)
     out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
-    with open(KERNEL_SRC, "rb") as fh:
-        out["source_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+    out["source_sha256"] = source_sha(hashlib)
     out["commands"] = [
         "rocprofv3 --pmc %s --output-format csv -d gpurun_out/pmc_%s -o %s -- python3 bench.py --steps 1 "
         "--warmup 0 --no-cpu-baseline --no-planted --no-f32 --copy-calibration" % (c, c.split("_")[0].lower(),

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["clusters.hip", "linalg.hip", "env.hip", "beam.hip", "adjoint.hip", "droplets.hip", "lbp.hip"]
+SOURCES = ["clusters.hip", "linalg.hip", "gemm_mfma.hip", "env.hip", "beam.hip", "adjoint.hip", "droplets.hip", "lbp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -67,8 +67,10 @@ struct Operand {
 };
 
 // C(m, n) = alpha * sum_k A(m, k) B(k, n) + beta * C(m, n) for every batch,
-// on the FP64 matrix cores (16x16x4 MFMA), 128 x 64 output tiles, each tile
-// owned by one workgroup and summed over all of K in order (deterministic).
+// on the FP64 matrix cores (16x16x4 MFMA), in 128 x 64, 128 x 128 or 64 x 64
+// output tiles (chosen per shape by the autotuner; defined in gemm_mfma.hip),
+// each tile owned by one workgroup and summed over all of K in order, so the
+// result is deterministic and the same for every tile choice.
 // tag selects a separately named kernel instance (same code): 0 general,
 // 1 .. 5 the mediating diagram's G2, out, Y2, W2 and left-transfer products.
 void gemm_mfma(int batch, int M, int N, int K, const Operand& A, const Operand& B, double* C, Ix cr, Ix cc,
