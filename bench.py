@@ -54,8 +54,8 @@ ROCPROF_NAME = {"medf_Y2": "medf_bin_pipe<0, 1, 0, double>", "medf_W2": "medf_bi
                 "medf_lbin": "medf_bin_pipe<0, 1, 1, double>", "medf_G2g": "gemm_mfma_kernel<1,",
                 "medf_outg": "gemm_mfma_kernel<2,", "medf_Y2g": "gemm_mfma_kernel<3,",
                 "medf_W2g": "gemm_mfma_kernel<4,", "medf_lbing": "gemm_mfma_kernel<5,",
-                "medf_Y2w": "medf_wsum_kernel<0>",
-                "medf_W2w": "medf_wsum_kernel<1>"}
+                "medf_Y2w": "medf_wsum_kernel<0,",
+                "medf_W2w": "medf_wsum_kernel<1,"}
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by the same counters on a plain copy of known size.

@@ -1415,22 +1415,44 @@ __global__ void gather_rho_kernel(const double* __restrict__ Y, Split sp, int nr
 // MODE 1 (applyT): o = hL, h = hR group: W = Wh(h(rd, h), h'(b', hL))
 // One workgroup per (rd, b') pair; the weights go through LDS, each thread
 // keeps the nh values of one element in registers and sums them in order.
-template <int MODE>
+// Bit extraction acts bit by bit, so pext(fr | pdep(hr), P) is the OR of
+// pext(fr, P) (one per workgroup) and pext(pdep(hr), P) (a table over hr,
+// built once per workgroup): with at most 64 groups a side the weight
+// lookups need no bit loops.
+// W takes nO * nh doubles of dynamic LDS and HMAX (16 or 32) bounds nh, so
+// small group counts keep the register and LDS footprint, and with it the
+// occupancy that hides the loads, small.
+template <int MODE, int HMAX>
 __global__ void __launch_bounds__(256) medf_wsum_kernel(MedF f, const double* __restrict__ S, int blk,
                                                         double* __restrict__ out) {
-  constexpr int HMAX = 32, WMAX = 4096;
-  __shared__ double W[WMAX];
+  constexpr int TMAX = 64;
+  extern __shared__ double W[];
+  __shared__ uint32_t TR[TMAX], TL[TMAX];
   const RowGeom::Med& md = f.md;
   const uint32_t pair = blockIdx.x;
   const uint32_t rd = pair / md.db2, b2 = pair % md.db2;
   const int nO = MODE == 0 ? f.nHR : f.nHL, nh = MODE == 0 ? f.nHL : f.nHR;
   const uint32_t fr = pdep_dev(rd, md.pos_d_rho), fl = pdep_dev(b2, md.pos_b2);
-  for (int i = threadIdx.x; i < nO * nh; i += blockDim.x) {
-    const uint32_t o = uint32_t(i / nh), h = uint32_t(i % nh);
-    const uint32_t hr = MODE == 0 ? o : h, hl = MODE == 0 ? h : o;
-    const uint32_t lh = pext_dev(fr | pdep_dev(hr, f.hR_pos), md.pos_h_rho);
-    const uint32_t hp = pext_dev(fl | pdep_dev(hl, f.hL_pos), md.pos_h_ell);
-    W[i] = md.Wh[lh * md.Wh_sp + hp * md.Wh_sq];
+  if (f.nHR <= TMAX && f.nHL <= TMAX) {
+    const uint32_t uR = pext_dev(fr, md.pos_h_rho), uL = pext_dev(fl, md.pos_h_ell);
+    for (int i = threadIdx.x; i < f.nHR + f.nHL; i += blockDim.x) {
+      if (i < f.nHR) TR[i] = pext_dev(pdep_dev(uint32_t(i), f.hR_pos), md.pos_h_rho);
+      else TL[i - f.nHR] = pext_dev(pdep_dev(uint32_t(i - f.nHR), f.hL_pos), md.pos_h_ell);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nO * nh; i += blockDim.x) {
+      const uint32_t o = uint32_t(i / nh), h = uint32_t(i % nh);
+      const uint32_t hr = MODE == 0 ? o : h, hl = MODE == 0 ? h : o;
+      W[i] = md.Wh[(uR | TR[hr]) * md.Wh_sp + (uL | TL[hl]) * md.Wh_sq];
+    }
+  } else {
+    for (int i = threadIdx.x; i < nO * nh; i += blockDim.x) {
+      const uint32_t o = uint32_t(i / nh), h = uint32_t(i % nh);
+      const uint32_t hr = MODE == 0 ? o : h, hl = MODE == 0 ? h : o;
+      const uint32_t lh = pext_dev(fr | pdep_dev(hr, f.hR_pos), md.pos_h_rho);
+      const uint32_t hp = pext_dev(fl | pdep_dev(hl, f.hL_pos), md.pos_h_ell);
+      W[i] = md.Wh[lh * md.Wh_sp + hp * md.Wh_sq];
+    }
   }
   __syncthreads();
   const int64_t hs = int64_t(md.db2) * md.drd * blk;
@@ -1801,7 +1823,13 @@ struct Zipper {
     const int nO = MODE == 0 ? f.nHR : f.nHL, nh = MODE == 0 ? f.nHL : f.nHR;
     const double pairs = double(md.drd) * md.db2;
     KTimer _t(timer, st, pairs * 2.0 * nO * nh * blk, pairs * 8.0 * double(nO + nh) * blk);
-    hipLaunchKernelGGL(medf_wsum_kernel<MODE>, dim3(unsigned(md.drd * md.db2)), dim3(256), 0, st, f, Sg.p, blk, out);
+    const size_t shm = size_t(nO) * nh * sizeof(double);
+    if (nh <= 16)
+      hipLaunchKernelGGL((medf_wsum_kernel<MODE, 16>), dim3(unsigned(md.drd * md.db2)), dim3(256), shm, st, f, Sg.p,
+                         blk, out);
+    else
+      hipLaunchKernelGGL((medf_wsum_kernel<MODE, 32>), dim3(unsigned(md.drd * md.db2)), dim3(256), shm, st, f, Sg.p,
+                         blk, out);
     HIPC(hipGetLastError());
   }
 
