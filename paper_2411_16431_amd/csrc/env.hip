@@ -1028,22 +1028,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) s
   }
 }
 
+// The free values f of a block u are split in chunks of fchunk over
+// blockIdx.y (few blocks with many free values would leave the chip idle);
+// with more than one chunk each workgroup writes its partial sum to
+// part[chunk][u] and sum_parts_kernel adds the chunks in order.
 template <int NJ, class T = double>
 __global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL,
                                                         uint32_t PR, uint32_t Bdn, const T* __restrict__ w,
                                                         const T* __restrict__ A, int Da, int Db,
                                                         const T* __restrict__ Kc, int Dg,
                                                         const T* __restrict__ Y, int s,
-                                                        T* __restrict__ G) {
+                                                        T* __restrict__ G, int fchunk, T* __restrict__ part) {
   __shared__ T red[4][32][16 * NJ];
   const int lane = threadIdx.x & 63, w4 = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
   const uint32_t u = blockIdx.x;
+  const int f0 = int(blockIdx.y) * fchunk, f1 = f0 + fchunk < nfree ? f0 + fchunk : nfree;
   typename MF<T>::v4 acc[2][NJ];
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[m][j] = MF<T>::zero();
-  for (int f = w4; f < nfree; f += 4) {
+  for (int f = f0 + w4; f < f1; f += 4) {
     const uint32_t x = pdep_dev(u, Bup) | pdep_dev(uint32_t(f), FREE);
     const T wx = w[x];
     if (wx == 0.0) continue;
@@ -1083,11 +1088,21 @@ __global__ void __launch_bounds__(256) site_applyT_mfma(uint32_t Bup, uint32_t F
 #pragma unroll
       for (int v = 0; v < 4; ++v) red[w4][16 * m + MF<T>::row(v, lk)][16 * j + li] = acc[m][j][v];
   __syncthreads();
-  T* o = G + size_t(u) * Dg * s;
+  T* o = gridDim.y == 1 ? G + size_t(u) * Dg * s : part + (size_t(blockIdx.y) * gridDim.x + u) * Dg * s;
   for (int i = threadIdx.x; i < 32 * 16 * NJ; i += 256) {
     const int g = i / (16 * NJ), jj = i % (16 * NJ);
     if (g < Dg && jj < s) o[size_t(g) * s + jj] = red[0][g][jj] + red[1][g][jj] + red[2][g][jj] + red[3][g][jj];
   }
+}
+
+// out[i] = sum over c < nparts, in order, of part[c][i]
+template <class T>
+__global__ void sum_parts_kernel(const T* __restrict__ part, int nparts, int64_t n, T* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T acc = part[i];
+  for (int c = 1; c < nparts; ++c) acc += part[c * n + i];
+  out[i] = acc;
 }
 
 // out[n][c][r] = in[n][r][c] for n < count (per-item transpose of r x c blocks)
@@ -1509,6 +1524,7 @@ struct Zipper {
   DevBuf<double> Pq, AT, AT2, LT, QU, Mw, Uw, Sw, VTw, L1, C1, Xc;
   DevBuf<double> cA, cK, cX, cO;  // operands and output of a diagram in FP32 mode (storage only)
   DevBuf<double> Sg;              // per-group sums of the grouped products
+  DevBuf<double> Pt;              // partial sums of the site transpose over chunks of free values
   Site phiL;
   std::vector<DevBuf<double>> cn;  // cn[k]: connector / right environment of the box at k-1 (cn[K] = 1)
   std::vector<DevBuf<double>> Lv;  // left environments of the sweeps
@@ -1620,11 +1636,21 @@ struct Zipper {
   void launch_site_applyT(int s, unsigned grid, uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL, uint32_t PR,
                           uint32_t Bdn, const T* w, const T* A, int Da, int Db, const T* Kc, int Dg, const T* Y,
                           T* G) {
+    // chunks of at least 64 free values, enough of them for ~2048 workgroups
+    int nchunk = 1;
+    if (grid < 2048u && nfree >= 128) {
+      nchunk = int((2048u + grid - 1) / grid);
+      if (nchunk > nfree / 64) nchunk = nfree / 64;
+    }
+    const int fchunk = (nfree + nchunk - 1) / nchunk;
+    nchunk = (nfree + fchunk - 1) / fchunk;
+    const int64_t nout = int64_t(grid) * Dg * s;
+    T* part = nchunk > 1 ? tb<T>(Pt, size_t(nout) * nchunk) : nullptr;
     switch ((s + 15) / 16) {
-#define TNB_SITET_CASE(NJV)                                                                                 \
-  case NJV:                                                                                                 \
-    hipLaunchKernelGGL((site_applyT_mfma<NJV, T>), dim3(grid), dim3(256), 0, st, Bup, FREE, nfree, PL, PR,  \
-                       Bdn, w, A, Da, Db, Kc, Dg, Y, s, G);                                                  \
+#define TNB_SITET_CASE(NJV)                                                                                   \
+  case NJV:                                                                                                   \
+    hipLaunchKernelGGL((site_applyT_mfma<NJV, T>), dim3(grid, unsigned(nchunk)), dim3(256), 0, st, Bup, FREE, \
+                       nfree, PL, PR, Bdn, w, A, Da, Db, Kc, Dg, Y, s, G, fchunk, part);                       \
     break;
       TNB_SITET_CASE(1)
       TNB_SITET_CASE(2)
@@ -1632,6 +1658,11 @@ struct Zipper {
       TNB_SITET_CASE(4)
 #undef TNB_SITET_CASE
       default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
+    }
+    if (nchunk > 1) {
+      HIPC(hipGetLastError());
+      hipLaunchKernelGGL((sum_parts_kernel<T>), dim3(unsigned((nout + 255) / 256)), dim3(256), 0, st, part, nchunk,
+                         nout, G);
     }
   }
   // The binned stage (Kd <= 32): variant 0 is medf_bin_pipe with one 16-column
