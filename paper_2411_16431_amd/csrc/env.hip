@@ -964,15 +964,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) s
                                                       const T* __restrict__ A, int Da, int Db,
                                                       const T* __restrict__ Kc, int Dg,
                                                       const T* __restrict__ Xt, int s,
-                                                      T* __restrict__ out) {
+                                                      T* __restrict__ out, int fchunk, T* __restrict__ part) {
   // one to four waves per output block; wave wv takes x = wv, wv + nw, ...
+  // of the chunk blockIdx.y of free values (partial sums as in site_applyT_mfma)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const uint32_t l = blockIdx.x;
+  const int f0 = int(blockIdx.y) * fchunk, f1 = f0 + fchunk < nfree ? f0 + fchunk : nfree;
   typename MF<T>::v4 acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::zero();
-  for (int f = wv; f < nfree; f += nw) {
+  for (int f = f0 + wv; f < f1; f += nw) {
     const uint32_t x = pdep_dev(l, PL) | pdep_dev(uint32_t(f), FREE);
     const T wx = w[x];
     if (wx == 0.0) continue;
@@ -1001,7 +1003,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) s
       for (int j = 0; j < NJ; ++j) acc[j] = MF<T>::mma(a, t[j][kk], acc[j]);
     }
   }
-  T* o = out + size_t(l) * Da * s;
+  T* o = gridDim.y == 1 ? out + size_t(l) * Da * s : part + (size_t(blockIdx.y) * gridDim.x + l) * Da * s;
   if (nw == 1) {  // uniform over the workgroup
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
@@ -1618,11 +1620,15 @@ struct Zipper {
                          T* out) {
     // four waves split the x values of a block once there are enough of them
     const unsigned threads = nfree >= 8 ? 256u : 64u;
+    int nchunk, fchunk;
+    free_chunks(grid, nfree, nchunk, fchunk);
+    const int64_t nout = int64_t(grid) * Da * s;
+    T* part = nchunk > 1 ? tb<T>(Pt, size_t(nout) * nchunk) : nullptr;
     switch ((s + 15) / 16) {
-#define TNB_SITE_CASE(NJV)                                                                                  \
-  case NJV:                                                                                                 \
-    hipLaunchKernelGGL((site_apply_mfma<NJV, VIEW, T>), dim3(grid), dim3(threads), 0, st, PL, FREE, nfree, \
-                       PR, Bup, Bdn, w, A, Da, Db, Kc, Dg, Xt, s, out);                                      \
+#define TNB_SITE_CASE(NJV)                                                                                    \
+  case NJV:                                                                                                   \
+    hipLaunchKernelGGL((site_apply_mfma<NJV, VIEW, T>), dim3(grid, unsigned(nchunk)), dim3(threads), 0, st,  \
+                       PL, FREE, nfree, PR, Bup, Bdn, w, A, Da, Db, Kc, Dg, Xt, s, out, fchunk, part);         \
     break;
       TNB_SITE_CASE(1)
       TNB_SITE_CASE(2)
@@ -1631,19 +1637,29 @@ struct Zipper {
 #undef TNB_SITE_CASE
       default: fail(TNB_EUNSUPPORTED, "sketch block wider than 64 columns");
     }
+    if (nchunk > 1) {
+      HIPC(hipGetLastError());
+      hipLaunchKernelGGL((sum_parts_kernel<T>), dim3(unsigned((nout + 255) / 256)), dim3(256), 0, st, part, nchunk,
+                         nout, out);
+    }
+  }
+  // Chunks of the free values of a site diagram's blocks: at least 64 values
+  // each, enough of them for ~2048 workgroups when the blocks are few.
+  static void free_chunks(unsigned grid, int nfree, int& nchunk, int& fchunk) {
+    nchunk = 1;
+    if (grid < 2048u && nfree >= 128) {
+      nchunk = int((2048u + grid - 1) / grid);
+      if (nchunk > nfree / 64) nchunk = nfree / 64;
+    }
+    fchunk = (nfree + nchunk - 1) / nchunk;
+    nchunk = (nfree + fchunk - 1) / fchunk;
   }
   template <class T>
   void launch_site_applyT(int s, unsigned grid, uint32_t Bup, uint32_t FREE, int nfree, uint32_t PL, uint32_t PR,
                           uint32_t Bdn, const T* w, const T* A, int Da, int Db, const T* Kc, int Dg, const T* Y,
                           T* G) {
-    // chunks of at least 64 free values, enough of them for ~2048 workgroups
-    int nchunk = 1;
-    if (grid < 2048u && nfree >= 128) {
-      nchunk = int((2048u + grid - 1) / grid);
-      if (nchunk > nfree / 64) nchunk = nfree / 64;
-    }
-    const int fchunk = (nfree + nchunk - 1) / nchunk;
-    nchunk = (nfree + fchunk - 1) / fchunk;
+    int nchunk, fchunk;
+    free_chunks(grid, nfree, nchunk, fchunk);
     const int64_t nout = int64_t(grid) * Dg * s;
     T* part = nchunk > 1 ? tb<T>(Pt, size_t(nout) * nchunk) : nullptr;
     switch ((s + 15) / 16) {
