@@ -180,10 +180,34 @@ void dev_free(void* p, const Allocator* owner) {
 static bool g_prof = false;
 static std::vector<ProfRec> g_recs;
 static std::mutex g_prof_mu;  // calls on several host threads record concurrently
+// Free timing events per device (events belong to the device that was
+// current when they were created).  Records return theirs when cleared.
+constexpr int kPoolDevices = 64;
+static std::vector<hipEvent_t> g_pool[kPoolDevices];
+static std::vector<int> g_rec_dev;  // device of each record's events
 bool prof_on() { return g_prof; }
 void prof_push(const ProfRec& r) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lock(g_prof_mu);
   g_recs.push_back(r);
+  g_rec_dev.push_back(dev);
+}
+hipEvent_t prof_event() {
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kPoolDevices) fail(TNB_EDEVICE, "device index out of range");
+  {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    if (!g_pool[dev].empty()) {
+      hipEvent_t e = g_pool[dev].back();
+      g_pool[dev].pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e;
+  HIPC(hipEventCreate(&e));
+  return e;
 }
 
 // A weight of 1 in device memory (the site weight of a cluster's empty side):
@@ -497,11 +521,24 @@ extern "C" tnb_status tnb_profile_enable(int32_t on) {
   return guarded([&] {
     std::lock_guard<std::mutex> lock(tnb::g_prof_mu);
     if (on) {
-      for (auto& r : tnb::g_recs) {
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+      // the previous records' events go back to their device's pool, and the
+      // current device's pool is topped up to 16384 events before timing
+      for (size_t i = 0; i < tnb::g_recs.size(); ++i) {
+        auto& pool = tnb::g_pool[tnb::g_rec_dev[i]];
+        pool.push_back(tnb::g_recs[i].a);
+        pool.push_back(tnb::g_recs[i].b);
       }
       tnb::g_recs.clear();
+      tnb::g_rec_dev.clear();
+      int dev = 0;
+      HIPC(hipGetDevice(&dev));
+      if (dev < 0 || dev >= tnb::kPoolDevices) fail(TNB_EDEVICE, "device index out of range");
+      auto& pool = tnb::g_pool[dev];
+      while (pool.size() < 16384) {
+        hipEvent_t e;
+        HIPC(hipEventCreate(&e));
+        pool.push_back(e);
+      }
     }
     tnb::g_prof = on != 0;
   });

@@ -182,6 +182,9 @@ struct ProfRec {
 };
 bool prof_on();
 void prof_push(const ProfRec& r);
+// A timing event of the current device from a pool that is filled when
+// profiling is switched on, so that timed regions create no events.
+hipEvent_t prof_event();
 struct KTimer {
   bool on;
   ProfRec r;
@@ -189,8 +192,8 @@ struct KTimer {
   KTimer(const char* name, hipStream_t s, double flops, double bytes) : on(prof_on()), st(s) {
     r = ProfRec{name, nullptr, nullptr, flops, bytes};
     if (on) {
-      HIPC(hipEventCreate(&r.a));
-      HIPC(hipEventCreate(&r.b));
+      r.a = prof_event();
+      r.b = prof_event();
       HIPC(hipEventRecord(r.a, st));
     }
   }
