@@ -64,26 +64,30 @@ def test_full_size_dims(setup):
     assert pk.diagram_dims(cl, R_ROW, K_MED) == (65536, 65536, 256, 65536)
 
 
-def test_site_diagram_full_size(setup):
+# column 1 (k = 2) and the boundary column 0 (k = 0), whose few output
+# blocks take the launch that splits each block's cluster values over
+# several workgroups
+@pytest.mark.parametrize("k_site", [K_SITE, 0])
+def test_site_diagram_full_size(setup, k_site):
     pk, torch, inst, net, cl = setup
-    c = K_SITE // 2
+    c = k_site // 2
     ops = RowOps(net, R_ROW)
-    dm_in, dm_out, ds, dsb = pk.diagram_dims(cl, R_ROW, K_SITE)
+    dm_in, dm_out, ds, dsb = pk.diagram_dims(cl, R_ROW, k_site)
     rng = np.random.default_rng(11)
     A = rng.standard_normal((dsb, CHI_B, CHI_B))          # [sigma][a][b]
     Kc = rng.standard_normal((dm_out, CHI_B, DG))         # [rho][b][g]
     X = rng.standard_normal((ds, DG, S))                  # [v][g][j]
     Y = rng.standard_normal((dm_in, CHI_B, S))            # [l][a][j]
-    got = pk.diagram_apply(cl, R_ROW, K_SITE, 0, _dev(torch, A), _dev(torch, Kc), _dev(torch, X)).cpu().numpy()
+    got = pk.diagram_apply(cl, R_ROW, k_site, 0, _dev(torch, A), _dev(torch, Kc), _dev(torch, X)).cpu().numpy()
     ref = ops.site_apply(c, A.transpose(1, 0, 2), Kc.transpose(1, 0, 2), X).transpose(1, 0, 2)
     _close(got, ref, "site apply")
-    got = pk.diagram_apply(cl, R_ROW, K_SITE, 1, _dev(torch, A), _dev(torch, Kc), _dev(torch, Y)).cpu().numpy()
+    got = pk.diagram_apply(cl, R_ROW, k_site, 1, _dev(torch, A), _dev(torch, Kc), _dev(torch, Y)).cpu().numpy()
     ref = ops.site_applyT(c, A.transpose(1, 0, 2), Kc.transpose(1, 0, 2), Y.transpose(1, 0, 2))
     _close(got, ref, "site transpose")
     # left transfer: L [l][a][t] with t = DG, new site phi [v][t][g] with g = DG
     L = rng.standard_normal((dm_in, CHI_B, DG))
     phi = rng.standard_normal((ds, DG, DG))
-    got = pk.diagram_apply(cl, R_ROW, K_SITE, 2, _dev(torch, A), _dev(torch, L), _dev(torch, phi)).cpu().numpy()
+    got = pk.diagram_apply(cl, R_ROW, k_site, 2, _dev(torch, A), _dev(torch, L), _dev(torch, phi)).cpu().numpy()
     ref = ops.site_left(c, A.transpose(1, 0, 2), L.transpose(1, 0, 2), phi.transpose(1, 0, 2)).transpose(1, 0, 2)
     _close(got, ref, "site left transfer")
 
