@@ -38,7 +38,7 @@ WORKLOADS = {
 # MI355X: FP64 vector and FP64 MFMA peaks are equal; FP32 MFMA (dense) and FP32 vector are 157.3
 PEAK = {"alu_fp64_tflops": 78.6, "fp32_tflops": 157.3, "hbm_gbs": 8000.0}
 MFMA_KERNELS = {"medf_Y2", "medf_W2", "medf_Y2g", "medf_W2g", "medf_G2", "medf_out", "medf_G2g", "medf_outg",
-                "medf_lbin", "medf_lbing", "medf_lacc", "renv_V", "adj_v", "site_apply", "site_applyT", "site_left", "gemm"}
+                "medf_lbin", "medf_lbing", "medf_lacc", "medf_laccg", "renv_V", "adj_v", "site_apply", "site_applyT", "site_left", "gemm"}
 
 
 def peak_of(name):

@@ -1880,18 +1880,18 @@ struct Zipper {
     HIPC(hipGetLastError());
   }
 
-  // out[rho] (Da x s) from the site A [a' + da2 b'][a][b] and Y2 [rd][b'][hR][b][s]
-  void out_gemm(const RowGeom::Med& md, const MedF& f, const Site& A, const double* Y2, int Da, int Db, int s,
-                double* out) {
+  // out[rho] (Da x s) from the site A [a' + da2 b'][a][b] (nA doubles) and
+  // Y2 [rd][b'][hR][b][s]
+  void out_gemm(const RowGeom::Med& md, const MedF& f, const double* A, int64_t nA, const double* Y2, int Da, int Db,
+                int s, double* out, const char* timer = "medf_outg") {
     const Split sp = make_split(pext_host(f.hR_pos, md.pos_a2), md.da2);
     const int blk = Da * Db;
-    const int64_t nA = int64_t(A.size()), nC = int64_t(md.dR) * Da * s;
+    const int64_t nC = int64_t(md.dR) * Da * s;
     double* Ap = tb<double>(cA, size_t(nA));
     double* Cp = tb<double>(cO, size_t(nC));
     {
       KTimer _t("medf_perm", st, 0.0, 16.0 * double(nA));
-      hipLaunchKernelGGL(gather_site_kernel, dim3(blocks(nA)), dim3(256), 0, st, A.data.p, md.da2, md.db2, sp, blk,
-                         Ap);
+      hipLaunchKernelGGL(gather_site_kernel, dim3(blocks(nA)), dim3(256), 0, st, A, md.da2, md.db2, sp, blk, Ap);
     }
     const int M = sp.nrest * Da, N = md.drd * s, Kd = md.db2 * Db;
     la::Operand a{Ap, int64_t(sp.nrest) * md.db2 * blk, la::Ix{uint32_t(Da), int64_t(md.db2) * blk, Db},
@@ -1900,7 +1900,7 @@ struct Zipper {
                   la::Ix{uint32_t(s), int64_t(md.db2) * f.nHR * Db * s, 1}};
     la::gemm_mfma(sp.nh, M, N, Kd, a, b, Cp, la::Ix{uint32_t(Da), int64_t(md.drd) * Da * s, s},
                   la::Ix{uint32_t(s), int64_t(Da) * s, 1}, int64_t(sp.nrest) * md.drd * Da * s, 1.0, 0.0, st,
-                  "medf_outg", 2);
+                  timer, 2);
     {
       KTimer _t("medf_perm", st, 0.0, 16.0 * double(nC));
       hipLaunchKernelGGL(scatter_out_kernel, dim3(blocks(nC)), dim3(256), 0, st, Cp, sp, md.drd, md.pos_d_rho,
@@ -1995,7 +1995,7 @@ struct Zipper {
       }
       T* oT = out_T<T>(out, int64_t(md.dR) * Da * s, cO);
       if (sizeof(T) == sizeof(double) && out_gemm_ok(md, f)) {
-        out_gemm(md, f, A, reinterpret_cast<const double*>(YfT), Da, Db, s, out);
+        out_gemm(md, f, A.data.p, int64_t(A.size()), reinterpret_cast<const double*>(YfT), Da, Db, s, out);
       } else {
         KTimer _t2(TNB_TN("medf_out"), st, double(md.dR) * md.db2 * 2.0 * Da * Db * s,
                    sz * (double(md.da2) * md.db2 * Da * Db + double(md.drd) * md.db2 * f.nHR * Db * s +
@@ -2257,6 +2257,14 @@ struct Zipper {
                                 YfT);
         }
         HIPC(hipGetLastError());
+      }
+      if (sizeof(T) == sizeof(double) && out_gemm_ok(mm, f)) {
+        // the out product of the apply on the mirrored geometry: its site
+        // operand is the site with the physical split exchanged (AT) and
+        // each block transposed, [b' + db2 a'][b][a]
+        const double* ATt = transposed<double>(AT.p, int64_t(A.d), Da, Db, connT);
+        out_gemm(mm, f, ATt, int64_t(A.size()), reinterpret_cast<const double*>(YfT), Db, Da, s, out, "medf_laccg");
+        return;
       }
       T* oT = out_T<T>(out, int64_t(mm.dR) * Db * s, cO);
       {
