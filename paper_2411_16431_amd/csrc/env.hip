@@ -452,7 +452,8 @@ __global__ void __launch_bounds__(256) medf_acc_mfma(MedF f, const T* __restrict
 // MPS site as stored, MODE 0 a transposed copy of the connector, [l][g][b].
 template <int MODE, int NJ, class T>
 __device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict__ P, const T* __restrict__ Q, int Da,
-                                              int Db, int Kd, int s, T* __restrict__ out) {
+                                              int Db, int Kd, int s, T* __restrict__ out, int ichunk,
+                                              T* __restrict__ part) {
   constexpr int KK = 8, QS = 16 * NJ;  // reduction <= 4 * KK
   __shared__ T Ts[4][16][QS];
   __shared__ T Ws[4][16];
@@ -473,6 +474,9 @@ __device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict
   const int b0 = blockIdx.y * 16;
   const int nbins = min(16, nH - int(chunk) * 16);
   const int nitems = MODE == 0 ? md.dL / md.db2 : md.dR / md.drd;
+  // the class's items i0 .. i1-1: all of them, or (few output blocks) the
+  // chunk blockIdx.z, whose partial sum goes to part[blockIdx.z]
+  const int i0 = int(blockIdx.z) * ichunk, i1 = i0 + ichunk < nitems ? i0 + ichunk : nitems;
   const int nkk = (Kd + 3) >> 2;
   const int b = b0 + li;
   const int j0 = int(r8 % njt) * 16 * NJ;  // first sketch column of this workgroup
@@ -507,7 +511,7 @@ __device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict
   }
   T pa[KK], qb[KK][NJ], wr = 0;
   auto fetch = [&](int t) {
-    if (t >= nitems) return;
+    if (t >= i1) return;
     uint32_t item, xp, hp;
     if (tabbed) {
       item = fixed | tab_item[t];
@@ -547,13 +551,13 @@ __device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = MF<T>::zero();
-  fetch(w);
-  for (int t0 = 0; t0 < nitems; t0 += 4) {
+  fetch(i0 + w);
+  for (int t0 = i0; t0 < i1; t0 += 4) {
     const int t = t0 + w;
     typename MF<T>::v4 tt[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) tt[j] = MF<T>::zero();
-    const bool live = t < nitems;
+    const bool live = t < i1;
     const T wcur = live ? wr : T(0);
     if (live) {
 #pragma unroll
@@ -576,7 +580,8 @@ __device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict
 #pragma unroll
       for (int j = 0; j < NJ; ++j) acc[bl][j] = MF<T>::mma(a2, Ts[lk][4 * w + bl][16 * j + li], acc[bl][j]);
   }
-  T* o = out + (size_t(pair) * nH + chunk * 16u) * Db * s;
+  T* dst = gridDim.z == 1 ? out : part + size_t(blockIdx.z) * md.drd * md.db2 * nH * Db * s;
+  T* o = dst + (size_t(pair) * nH + chunk * 16u) * Db * s;
 #pragma unroll
   for (int bl = 0; bl < 4; ++bl) {
     const int bb = b0 + 4 * w + bl;
@@ -600,8 +605,8 @@ __device__ __forceinline__ void medf_bin_body(const MedF& f, const T* __restrict
 template <int MODE, int NJ, int VIEW = 0, class T = double>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) medf_bin_pipe(MedF f, const T* __restrict__ P,
                                                      const T* __restrict__ Q, int Da, int Db, int Kd, int s,
-                                                     T* __restrict__ out) {
-  medf_bin_body<MODE, NJ, T>(f, P, Q, Da, Db, Kd, s, out);
+                                                     T* __restrict__ out, int ichunk, T* __restrict__ part) {
+  medf_bin_body<MODE, NJ, T>(f, P, Q, Da, Db, Kd, s, out, ichunk, part);
 }
 
 // The same body with NJ column tiles per workgroup and no register cap: each
@@ -609,8 +614,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) m
 // two is faster depends on the shape; the autotuner decides.
 template <int MODE, int NJ, int VIEW = 0, class T = double>
 __global__ void __launch_bounds__(256) medf_bin_wide(MedF f, const T* __restrict__ P, const T* __restrict__ Q, int Da,
-                                                     int Db, int Kd, int s, T* __restrict__ out) {
-  medf_bin_body<MODE, NJ, T>(f, P, Q, Da, Db, Kd, s, out);
+                                                     int Db, int Kd, int s, T* __restrict__ out, int ichunk,
+                                                     T* __restrict__ part) {
+  medf_bin_body<MODE, NJ, T>(f, P, Q, Da, Db, Kd, s, out, ichunk, part);
 }
 
 // Grouped two-stage contraction.  The weight of item t depends on t only
@@ -1526,7 +1532,7 @@ struct Zipper {
   DevBuf<double> Pq, AT, AT2, LT, QU, Mw, Uw, Sw, VTw, L1, C1, Xc;
   DevBuf<double> cA, cK, cX, cO;  // operands and output of a diagram in FP32 mode (storage only)
   DevBuf<double> Sg;              // per-group sums of the grouped products
-  DevBuf<double> Pt;              // partial sums of the site transpose over chunks of free values
+  DevBuf<double> Pt;              // partial sums of launches split over chunks (site diagrams, binned stage)
   Site phiL;
   std::vector<DevBuf<double>> cn;  // cn[k]: connector / right environment of the box at k-1 (cn[K] = 1)
   std::vector<DevBuf<double>> Lv;  // left environments of the sweeps
@@ -1697,22 +1703,43 @@ struct Zipper {
       kinds[n++] = 3;
       if (nj >= 2) kinds[n++] = 4;
     }
+    // binned variants with few output blocks split each class's items in
+    // chunks of at least 32 over blockIdx.z (ordered partial sums)
+    const int nitems = MODE == 0 ? f.md.dL / f.md.db2 : f.md.dR / f.md.drd;
+    const int64_t nout = int64_t(f.md.drd) * f.md.db2 * (MODE == 0 ? f.nHR : f.nHL) * Db * s;
     auto run = [&](int vv) {
       const int v = kinds[vv];
       const int njv = v < 3 ? v + 1 : v - 2;
       const unsigned njt = unsigned((s + 16 * njv - 1) / (16 * njv));
-      const dim3 grid(((v < 3 ? G : Gg) + 7) / 8 * 8 * njt, unsigned((rows + 15) / 16));
+      const unsigned gx = ((v < 3 ? G : Gg) + 7) / 8 * 8 * njt, gy = unsigned((rows + 15) / 16);
+      int nz = 1;
+      if (v < 3 && gx * gy < 256u && nitems >= 64) {
+        nz = int((1024u + gx * gy - 1) / (gx * gy));
+        if (nz > nitems / 32) nz = nitems / 32;
+      }
+      const int ichunk = (nitems + nz - 1) / nz;
+      nz = (nitems + ichunk - 1) / ichunk;
+      T* part = nz > 1 ? tb<T>(Pt, size_t(nout) * nz) : nullptr;
+      const dim3 grid(gx, gy, unsigned(nz));
       if (v == 0)
-        hipLaunchKernelGGL((medf_bin_pipe<MODE, 1, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
+        hipLaunchKernelGGL((medf_bin_pipe<MODE, 1, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out,
+                           ichunk, part);
       else if (v == 1)
-        hipLaunchKernelGGL((medf_bin_wide<MODE, 2, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
+        hipLaunchKernelGGL((medf_bin_wide<MODE, 2, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out,
+                           ichunk, part);
       else if (v == 2)
-        hipLaunchKernelGGL((medf_bin_wide<MODE, 3, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
+        hipLaunchKernelGGL((medf_bin_wide<MODE, 3, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out,
+                           ichunk, part);
       else if (v == 3)
         hipLaunchKernelGGL((medf_grp<MODE, 1, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
       else
         hipLaunchKernelGGL((medf_grp<MODE, 2, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
       HIPC(hipGetLastError());
+      if (nz > 1) {
+        hipLaunchKernelGGL((sum_parts_kernel<T>), dim3(unsigned((nout + 255) / 256)), dim3(256), 0, st, part, nz,
+                           nout, out);
+        HIPC(hipGetLastError());
+      }
     };
 
     char key[160];
