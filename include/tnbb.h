@@ -292,7 +292,8 @@ tnb_status tnb_row_moments_per_branch(tnb_beam* beam, double* d_m1, int64_t m1_l
 /* Autotuner of kernel launch variants.  Some diagram stages have several
  * launch variants that compute the same sums and differ in how the work is
  * tiled over workgroups (sketch columns per workgroup of the binned mediating
- * kernel: bit-identical results) or in the order of their additions (the
+ * kernel: bit-identical results), GEMM tile shapes (bit-identical) or in the
+ * order of their additions (the
  * grouped mediating kernel, which sums the items of one weight group before
  * weighting them: equal up to rounding).  mode 1: the first launch of every
  * new shape times each candidate once with HIP events on the launch stream,

@@ -1704,23 +1704,27 @@ struct Zipper {
       if (nj >= 2) kinds[n++] = 4;
     }
     // binned variants with few output blocks split each class's items in
-    // chunks of at least 32 over blockIdx.z (ordered partial sums)
+    // chunks of at least 32 over blockIdx.z (ordered partial sums); the
+    // chunks do not depend on the variant, so the binned variants still give
+    // bit-identical results
     const int nitems = MODE == 0 ? f.md.dL / f.md.db2 : f.md.dR / f.md.drd;
     const int64_t nout = int64_t(f.md.drd) * f.md.db2 * (MODE == 0 ? f.nHR : f.nHL) * Db * s;
+    const unsigned gy = unsigned((rows + 15) / 16), gb = (G + 7) / 8 * 8 * gy;  // output blocks
+    int nz = 1;
+    if (gb < 256u && nitems >= 64) {
+      nz = int((1024u + gb - 1) / gb);
+      if (nz > nitems / 32) nz = nitems / 32;
+    }
+    const int ichunk = (nitems + nz - 1) / nz;
+    nz = (nitems + ichunk - 1) / ichunk;
     auto run = [&](int vv) {
       const int v = kinds[vv];
       const int njv = v < 3 ? v + 1 : v - 2;
       const unsigned njt = unsigned((s + 16 * njv - 1) / (16 * njv));
-      const unsigned gx = ((v < 3 ? G : Gg) + 7) / 8 * 8 * njt, gy = unsigned((rows + 15) / 16);
-      int nz = 1;
-      if (v < 3 && gx * gy < 256u && nitems >= 64) {
-        nz = int((1024u + gx * gy - 1) / (gx * gy));
-        if (nz > nitems / 32) nz = nitems / 32;
-      }
-      const int ichunk = (nitems + nz - 1) / nz;
-      nz = (nitems + ichunk - 1) / ichunk;
-      T* part = nz > 1 ? tb<T>(Pt, size_t(nout) * nz) : nullptr;
-      const dim3 grid(gx, gy, unsigned(nz));
+      const unsigned gx = ((v < 3 ? G : Gg) + 7) / 8 * 8 * njt;
+      const int nzv = v < 3 ? nz : 1;
+      T* part = nzv > 1 ? tb<T>(Pt, size_t(nout) * nzv) : nullptr;
+      const dim3 grid(gx, gy, unsigned(nzv));
       if (v == 0)
         hipLaunchKernelGGL((medf_bin_pipe<MODE, 1, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out,
                            ichunk, part);
@@ -1735,8 +1739,8 @@ struct Zipper {
       else
         hipLaunchKernelGGL((medf_grp<MODE, 2, VIEW, T>), grid, dim3(256), 0, st, f, P, Q, Da, Db, Kd, s, out);
       HIPC(hipGetLastError());
-      if (nz > 1) {
-        hipLaunchKernelGGL((sum_parts_kernel<T>), dim3(unsigned((nout + 255) / 256)), dim3(256), 0, st, part, nz,
+      if (nzv > 1) {
+        hipLaunchKernelGGL((sum_parts_kernel<T>), dim3(unsigned((nout + 255) / 256)), dim3(256), 0, st, part, nzv,
                            nout, out);
         HIPC(hipGetLastError());
       }

@@ -109,6 +109,35 @@ def test_every_variant_agrees_at_full_size(tmp_path):
             assert _rel(got[mode], base[mode]) <= TOL, (v, mode, _rel(got[mode], base[mode]))
 
 
+def test_binned_variants_identical_with_item_split(tmp_path):
+    # row 1, diagram k = 1 of Zephyr Z_2 t=4 (legs 4096 x 4096): few output
+    # blocks, so the binned stage splits each class's items over workgroups.
+    # The split does not depend on the variant: the binned variants (0..2)
+    # agree bit for bit, the grouped ones (3, 4) up to rounding, and the
+    # default variant's apply matches the oracle on sampled rows.
+    pk, torch = _gpu()
+    inst = make_instance("zephyr", 1000, jdist="uniform", hdist="uniform0.1", m=2, t=4)
+    net = Network(inst, 1.0)
+    cl = pk.Clusters(inst, 1.0)
+    r, k = 1, 1
+    t = _inputs(pk, cl, r, k, 91)
+    outs = {}
+    for v in _each_variant(pk, tmp_path, lambda: _run_all(pk, torch, cl, r, k, t)):
+        outs[v] = _run_all(pk, torch, cl, r, k, t)
+    for v in (1, 2):
+        for mode in range(3):
+            assert np.array_equal(outs[v][mode], outs[0][mode]), (v, mode)
+    for v in (3, 4):
+        for mode in range(3):
+            assert _rel(outs[v][mode], outs[0][mode]) <= TOL, (v, mode, _rel(outs[v][mode], outs[0][mode]))
+    ops = RowOps(net, r)
+    da, db = net.phys_dims(r)[1][k]
+    X_o = t["X"].reshape(db, da, DG, S).transpose(1, 0, 2, 3)
+    rhos = np.array([0, 1, 2047, 4095])
+    ref = ops.med_apply((k - 1) // 2, t["A"].transpose(1, 0, 2), t["K"].transpose(1, 0, 2), X_o, rhos=rhos)
+    assert _rel(outs[0][0][rhos], ref.transpose(1, 0, 2)) <= TOL
+
+
 def test_eigen_and_svd_launch_widths_agree(tmp_path):
     # the LDS eigensolver and one-sided Jacobi SVD of the Gram path (the
     # 2^16-state clusters of Zephyr t=4) at 16 and at 4 waves: the same
